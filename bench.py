@@ -1,0 +1,298 @@
+#!/usr/bin/env python3
+"""Benchmark of the CPR Euler hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+
+Workload (one "step" = one SSP-RK3 step = three fused residual + RK stage
+kernels over the whole mesh): CPR P=3 (4x4 Gauss-Legendre points per
+element), 2D Euler gamma=1.4, isentropic vortex (strength 5, free stream
+rho=p=1, u=v=1) on the periodic square [0,10]^2 with 256x256 elements
+(4,194,304 unknowns), Rusanov flux, Radau correction, synthetic analytic
+initial data. The metric is DOF-updates per second per RK stage (one
+unknown advanced by one stage), FP64 (the reported value) and FP32-bulk,
+with the L2 density error each reaches at t=10 (one period) on 64^2, 128^2
+and 256^2, and the hand-written adjoint's seconds per step on P=3 128^2.
+
+Printed: one JSON line (rank 0). Extra objects:
+  roofline      the stage kernel against HBM bandwidth (algorithmic bytes:
+                64 B per unknown per step = 21.33 B per unknown per launch)
+  cpu_baseline  the CPU oracle timed on a bounded sample of the workload
+  fp32_bulk, l2_error, adjoint, scale_p4_1024: see the keys.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("DOF-updates/s per RK stage (P=3, FP64 vs FP32-bulk) at fixed L2 error; "
+          "adjoint s/step")
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UNKNOWN_STEP = 64.0    # stage 1: 8 r + 8 w; stages 2, 3: 16 r + 8 w
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "stage_kernel_counters_p3_256.md")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def vortex_state(solver):
+    import torch
+    import inputs
+    x, y = solver.coords()
+    q = inputs.Vortex().conserved(x.cpu().numpy(), y.cpu().numpy())
+    return torch.from_numpy(q).to(solver.device)
+
+
+def c2_dt(solver, q, cfl=0.05, t_end=10.0):
+    """dt = CFL h / max(|u|+c) at t=0, rounded down so that t_end is hit."""
+    lam = solver.max_wavespeed(q)
+    dt = cfl * min(solver.dx, solver.dy) / lam
+    n = int(math.ceil(t_end / dt))
+    return t_end / n, n
+
+
+def time_steps(solver, q, dt, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        solver.step(q, dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        solver.step(q, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps   # ms per step
+
+
+def read_counters(src_sha):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("bench-key:"):
+            k, _, v = line[len("bench-key:"):].strip().partition("=")
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha") != src_sha:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1709_01619_amd", "csrc")
+    for f in ("cpr_device.h", "cpr_stage.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(P=3, n=256, steps=None, budget_s=15.0):
+    """The oracle (NumPy FP64, one BLAS thread) on the same workload: a
+    bounded number of RK3 steps on the full 256^2 mesh."""
+    import numpy as np
+    import inputs
+    from oracle import cpr
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:
+        limiter = None
+    g = cpr.Grid(P=P, nx=n, ny=n)
+    x, y = g.coords()
+    q = inputs.Vortex().conserved(x, y)
+    dt = 1e-3
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        q = cpr.rk3_step(q, dt, g)
+        done += 1
+        el = time.perf_counter() - t0
+        if (steps is not None and done >= steps) or (steps is None and el > budget_s):
+            break
+    el = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    U = g.n_unknowns
+    return {
+        "value": 3.0 * U * done / el,
+        "unit": "DOF-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{done} SSP-RK3 steps of the full 256x256 P=3 vortex mesh "
+                  f"({U} unknowns), NumPy float64, 1 BLAS thread, {el:.1f} s",
+        "s_per_step": el / done,
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the t=10 error runs, the adjoint and the P=4 legs")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU; the path has no multi-GPU mode "
+              "(--gpus must be 1)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1709_01619_amd import Rollout, Solver
+
+    torch.cuda.init()
+    out = {}
+    P, n = 3, 256
+
+    # ---- headline: P=3 256^2 FP64 and FP32-bulk ----
+    res = {}
+    for prec in ("fp64", "fp32_bulk"):
+        s = Solver(P, n, n, precision=prec)
+        q = vortex_state(s)
+        dt, _ = c2_dt(s, q)
+        ms = time_steps(s, q, dt, a.steps, a.warmup)
+        s.sync()
+        U = s.n_unknowns
+        res[prec] = {"ms_per_step": ms, "dof_updates_per_s": 3.0 * U / (ms * 1e-3),
+                     "stage_launch_us": ms * 1e3 / 3.0, "dt": dt}
+        log(prec, f"{ms:.4f} ms/step", f"{res[prec]['dof_updates_per_s']:.4e} DOF-updates/s/stage")
+        del s, q
+    U = 4 * n * n * (P + 1) ** 2
+    f64 = res["fp64"]
+    bytes_per_launch = BYTES_PER_UNKNOWN_STEP / 3.0 * U
+    achieved = bytes_per_launch / (f64["stage_launch_us"] * 1e-6) / 1e9
+    traffic = read_counters(kernel_source_sha())
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": "cpr::stage_kernel<3,double,0>",
+                "note": "256^2 P=3 states are 33.6 MB each, so the three live states fit the "
+                        "256 MB Infinity Cache; see scale_p4_1024 for an HBM-resident case"}
+
+    # ---- L2 error at t=10 (one period), FP64 vs FP32-bulk ----
+    l2 = None
+    if not a.quick:
+        l2 = {}
+        for prec in ("fp64", "fp32_bulk"):
+            errs = []
+            for m in (64, 128, 256):
+                s = Solver(P, m, m, precision=prec)
+                q0 = vortex_state(s)
+                q = q0.clone()
+                dt, nst = c2_dt(s, q)
+                t0 = time.perf_counter()
+                for _ in range(nst):
+                    s.step(q, dt)
+                e = s.l2_diff(q, q0, 0)
+                errs.append(e)
+                log(f"l2 {prec} {m}^2: {nst} steps, err {e:.4e}, {time.perf_counter() - t0:.2f} s")
+                del s, q, q0
+            orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+            l2[prec] = {"meshes": [64, 128, 256], "l2_rho": errs, "observed_order": orders}
+
+    # ---- adjoint: P=3 128^2, 400 steps, dt=1e-3, checkpoint every 50 ----
+    adj = None
+    if not a.quick:
+        import inputs
+        s = Solver(3, 128, 128)
+        x, y = s.coords()
+        V = inputs.Vortex()
+        q0n = V.conserved(x.cpu().numpy(), y.cpu().numpy())
+        q0n[0] += inputs.gaussian_perturbation(q0n[0].shape, 1e-3, 0)
+        rho_ex = torch.from_numpy(V.conserved(x.cpu().numpy(), y.cpu().numpy(), 0.4)[0]).cuda()
+        W = s.quad_weights()
+        q0 = torch.from_numpy(q0n).cuda().requires_grad_(True)
+        for rep in range(2):   # first pass warms up
+            if q0.grad is not None:
+                q0.grad = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            qT = Rollout.apply(q0, s, 1e-3, 400, 50)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            J = 0.5 * ((qT[0] - rho_ex) ** 2 * W).sum()
+            J.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+        adj = {"workload": "P=3 128x128 perturbed vortex, 400 steps dt=1e-3, checkpoint 50",
+               "forward_s_per_step": (t1 - t0) / 400, "backward_s_per_step": (t2 - t1) / 400,
+               "adjoint_s_per_step": (t2 - t0) / 400, "misfit": float(J.item())}
+        log("adjoint", adj)
+        del s
+
+    # ---- scale: P=4 1024^2 (104.9M unknowns), FP64 and FP32-bulk ----
+    scale = None
+    if not a.quick:
+        scale = {}
+        for prec in ("fp64", "fp32_bulk"):
+            s = Solver(4, 1024, 1024, precision=prec)
+            q = vortex_state(s)
+            ms = time_steps(s, q, 1e-4, 20, 3)
+            s.sync()
+            U4 = s.n_unknowns
+            ach = BYTES_PER_UNKNOWN_STEP / 3.0 * U4 / (ms * 1e-3 / 3.0) / 1e9
+            scale[prec] = {"ms_per_step": ms, "dof_updates_per_s": 3.0 * U4 / (ms * 1e-3),
+                           "roofline": {"bound": "hbm", "achieved": round(ach, 1),
+                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": round(ach / HBM_PEAK_GBS, 4)}}
+            log("p4 1024", prec, scale[prec])
+            del s, q
+
+    cpu = None
+    if not a.no_cpu:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline()
+        log("cpu", cpu)
+
+    line = {
+        "metric": METRIC,
+        "value": f64["dof_updates_per_s"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "CPR P=3 isentropic vortex, periodic [0,10]^2, 256x256 "
+                               "elements, 4194304 unknowns, SSP-RK3 (3 fused stage kernels "
+                               "per step), Rusanov, Radau, FP64",
+                   "P": P, "mesh": [n, n], "unknowns": U, "dt": f64["dt"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp32_bulk": {"value": res["fp32_bulk"]["dof_updates_per_s"],
+                      "ms_per_step": res["fp32_bulk"]["ms_per_step"],
+                      "speedup_vs_fp64": res["fp32_bulk"]["dof_updates_per_s"] / f64["dof_updates_per_s"]},
+        "l2_error_t10": l2,
+        "adjoint": adj,
+        "scale_p4_1024": scale,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -132,7 +132,7 @@ def entropy_wave(x, y, t=0.0, amp=0.2, L=10.0, u=1.0, v=1.0, p=1.0, gamma=GAMMA)
 # Seeded random inputs.
 # ----------------------------------------------------------------------------
 
-def random_state(shape, seed, rho=(0.8, 1.2), vel=(-0.4, 0.4), p=(0.8, 1.2),
+def random_state(shape, seed, rho=(0.85, 1.15), vel=(-0.3, 0.3), p=(0.85, 1.15),
                  gamma=GAMMA):
     """Independent uniform primitive values at every point, converted to
     conserved form; returns an array of shape (4,) + shape. The default

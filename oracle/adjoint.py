@@ -4,9 +4,13 @@
 residual_vjp(q, v) returns (dR/dq)^T v for the residual of oracle.cpr,
 transposing each of its operations in reverse order: flux evaluation,
 extrapolation to the faces, the Rusanov flux (including the derivative of
-its wave-speed bound lam = max(|u_n|+c) with the forward's branches: ties go
-to the left state, sign(0) = +1), the correction lift and the derivative
-contraction. rk3_adjoint_step transposes the Shu-Osher stages:
+its wave-speed bound lam = max(|u_n|+c); sign(0) = +1 for |u_n|), the
+correction lift and the derivative contraction. Where the two one-sided
+speeds tie, |lamL - lamR| <= 1e-12 max(lamL, lamR), max is not
+differentiable and its gradient is taken as the mean of the two sides'
+gradients (a valid subgradient that does not depend on which side rounding
+happens to favour; such ties occur exactly on the symmetry lines of the
+isentropic vortex). rk3_adjoint_step transposes the Shu-Osher stages:
     lam2 = 2/3 (lam3 + dt J(q2)^T lam3)
     lam1 = 1/4 (lam2 + dt J(q1)^T lam2)
     lamn = lam1 + dt J(qn)^T lam1 + 1/3 lam3 + 3/4 lam2
@@ -20,6 +24,8 @@ import numpy as np
 
 from . import cpr, euler
 from .cpr import PERIODIC, Grid
+
+TIE_REL = 1e-12   # relative gap below which the two Rusanov speeds count as tied
 
 
 def _jac_t_apply(q, s, gamma, axis):
@@ -49,13 +55,15 @@ def rusanov_vjp(qL, qR, s, gamma, axis):
     """Cotangents (of qL, of qR) of the Rusanov flux for output cotangent s."""
     lamL = euler.normal_wave_speed(qL, gamma, axis)
     lamR = euler.normal_wave_speed(qR, gamma, axis)
-    left_wins = lamL >= lamR
-    lam = np.where(left_wins, lamL, lamR)
+    lam = np.where(lamL >= lamR, lamL, lamR)
+    tie = np.abs(lamL - lamR) <= TIE_REL * np.maximum(lamL, lamR)
+    wL = np.where(tie, 0.5, np.where(lamL > lamR, 1.0, 0.0))
+    wR = 1.0 - wL
     jump = np.sum(s * (qR - qL), axis=0)
     cL = 0.5 * _jac_t_apply(qL, s, gamma, axis) + 0.5 * lam * s
     cR = 0.5 * _jac_t_apply(qR, s, gamma, axis) - 0.5 * lam * s
-    cL = cL - 0.5 * jump * np.where(left_wins, 1.0, 0.0) * _wave_speed_grad(qL, gamma, axis)
-    cR = cR - 0.5 * jump * np.where(left_wins, 0.0, 1.0) * _wave_speed_grad(qR, gamma, axis)
+    cL = cL - 0.5 * jump * wL * _wave_speed_grad(qL, gamma, axis)
+    cR = cR - 0.5 * jump * wR * _wave_speed_grad(qR, gamma, axis)
     return cL, cR
 
 

@@ -1,0 +1,430 @@
+// Limiter, reductions and helpers for the CPR library (gfx950).
+//
+// Limiter (Section 2.6 of arXiv:1709.01619, eq. limu, in the TVB
+// characteristic form of Cockburn and Shu that the paper cites): a means
+// pass writes every element's average; a second pass, one lane per element,
+// forms the face means of the extrapolated state, tests the face deviations
+// against the neighbour differences on characteristic variables with the
+// TVB minmod, and rewrites troubled elements as qbar + (x-x_I) s_x +
+// (y-y_J) s_y with characteristic minmod slopes.
+#include "cpr_device.h"
+
+namespace cpr {
+
+template <int N1>
+struct WTab {
+  double w[N1];
+  double xi[N1];
+  double em[N1];
+  double ep[N1];
+};
+
+template <int N1>
+static WTab<N1> make_wtab(const Tables1D& T) {
+  WTab<N1> t;
+  for (int i = 0; i < N1; ++i) {
+    t.w[i] = T.w[i];
+    t.xi[i] = T.xi[i];
+    t.em[i] = T.em[i];
+    t.ep[i] = T.ep[i];
+  }
+  return t;
+}
+
+// ---------------------------------------------------------------- means --
+template <int P>
+__global__ __launch_bounds__(256) void means_kernel(Geometry G, WTab<P + 1> W, LimitArgs A) {
+  constexpr int N1 = P + 1, NSP = N1 * N1;
+  if (A.skip != nullptr && *A.skip != 0) return;
+  const int ne = G.nx * G.ny;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const size_t plane = (size_t)ne * NSP;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* q = A.q + k * plane + (size_t)e * NSP;
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      double r = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) r += W.w[i] * q[j * N1 + i];
+      s += W.w[j] * r;
+    }
+    A.qbar[k * ne + e] = 0.25 * s;
+  }
+}
+
+// Right (R) and left (L = R^-1) eigenvectors of the flux Jacobian in
+// direction AX at state qb, rows/columns in (rho, rho u, rho v, e) order.
+template <int AX>
+__device__ void char_mats(const double qb[4], double gamma, double Rm[4][4], double Lm[4][4]) {
+  const double rho = qb[0];
+  const double u = qb[1] / rho, v = qb[2] / rho;
+  const double ke = 0.5 * (u * u + v * v);
+  const double p = (gamma - 1.0) * (qb[3] - rho * ke);
+  const double c = sqrt(gamma * p / rho);
+  const double H = (qb[3] + p) / rho;
+  const double b1 = (gamma - 1.0) / (c * c);
+  const double b2 = ke * b1;
+  const double un = AX == 0 ? u : v;
+  const double ut = AX == 0 ? v : u;
+  constexpr int in = AX == 0 ? 1 : 2;  // normal momentum index
+  constexpr int it = AX == 0 ? 2 : 1;  // tangential momentum index
+  const double rn[4][4] = {{1.0, 1.0, 0.0, 1.0},
+                           {un - c, un, 0.0, un + c},
+                           {ut, ut, 1.0, ut},
+                           {H - un * c, ke, ut, H + un * c}};
+  const double ln[4][4] = {{0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), -0.5 * b1 * ut, 0.5 * b1},
+                           {1.0 - b2, b1 * un, b1 * ut, -b1},
+                           {-ut, 0.0, 1.0, 0.0},
+                           {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), -0.5 * b1 * ut, 0.5 * b1}};
+  const int map[4] = {0, in, it, 3};  // (rho, m_n, m_t, e) -> variable index
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      Rm[map[a]][b] = rn[a][b];
+      Lm[a][map[b]] = ln[a][b];
+    }
+}
+
+__device__ __forceinline__ double minmod3(double a, double b, double c) {
+  const bool pos = a > 0.0 && b > 0.0 && c > 0.0;
+  const bool neg = a < 0.0 && b < 0.0 && c < 0.0;
+  const double m = fmin(fmin(fabs(a), fabs(b)), fabs(c));
+  return pos ? m : (neg ? -m : 0.0);
+}
+
+__device__ __forceinline__ void matvec(const double M[4][4], const double x[4], double y[4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a) y[a] = M[a][0] * x[0] + M[a][1] * x[1] + M[a][2] * x[2] + M[a][3] * x[3];
+}
+
+// ---------------------------------------------------- detect and limit --
+template <int P>
+__global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, LimitArgs A) {
+  constexpr int N1 = P + 1, NSP = N1 * N1;
+  if (A.skip != nullptr && *A.skip != 0) return;
+  const int ne = G.nx * G.ny;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int I = e % G.nx, J = e / G.nx;
+  const size_t plane = (size_t)ne * NSP;
+
+  double qb[4], fW[4], fE[4], fS[4], fN[4], nW[4], nE[4], nS[4], nN[4];
+  int Iw = I - 1, Ie = I + 1, Js = J - 1, Jn = J + 1;
+  if (G.periodic) {
+    Iw = (Iw + G.nx) % G.nx; Ie = Ie % G.nx;
+    Js = (Js + G.ny) % G.ny; Jn = Jn % G.ny;
+  } else {
+    Iw = max(Iw, 0); Ie = min(Ie, G.nx - 1);
+    Js = max(Js, 0); Jn = min(Jn, G.ny - 1);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double* q = A.q + k * plane + (size_t)e * NSP;
+    double w_ = 0.0, e_ = 0.0, s_ = 0.0, n_ = 0.0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      double rw = 0.0, re = 0.0, cs = 0.0, cn = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        rw += W.em[i] * q[j * N1 + i];   // row j extrapolated west
+        re += W.ep[i] * q[j * N1 + i];
+        cs += W.em[i] * q[i * N1 + j];   // column j extrapolated south
+        cn += W.ep[i] * q[i * N1 + j];
+      }
+      w_ += W.w[j] * rw;
+      e_ += W.w[j] * re;
+      s_ += W.w[j] * cs;
+      n_ += W.w[j] * cn;
+    }
+    fW[k] = 0.5 * w_;
+    fE[k] = 0.5 * e_;
+    fS[k] = 0.5 * s_;
+    fN[k] = 0.5 * n_;
+    qb[k] = A.qbar[k * ne + e];
+    nW[k] = A.qbar[k * ne + J * G.nx + Iw];
+    nE[k] = A.qbar[k * ne + J * G.nx + Ie];
+    nS[k] = A.qbar[k * ne + Js * G.nx + I];
+    nN[k] = A.qbar[k * ne + Jn * G.nx + I];
+  }
+  if (!(qb[0] > 0.0)) {
+    atomicOr(A.err, 1);
+    return;
+  }
+
+  bool troubled = false;
+  double slope[2][4];
+#pragma unroll
+  for (int ax = 0; ax < 2; ++ax) {
+    double Rm[4][4], Lm[4][4];
+    if (ax == 0) char_mats<0>(qb, G.gamma, Rm, Lm); else char_mats<1>(qb, G.gamma, Rm, Lm);
+    const double* lo = ax == 0 ? fW : fS;
+    const double* hi = ax == 0 ? fE : fN;
+    const double* nlo = ax == 0 ? nW : nS;
+    const double* nhi = ax == 0 ? nE : nN;
+    const double h = ax == 0 ? G.dx : G.dy;
+    double t0[4], t1[4], t2[4], t3[4], t4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      t0[k] = hi[k] - qb[k];
+      t1[k] = qb[k] - lo[k];
+      t2[k] = nhi[k] - qb[k];
+      t3[k] = qb[k] - nlo[k];
+      t4[k] = hi[k] - lo[k];
+    }
+    double up[4], um[4], dp[4], dm[4], dd[4];
+    matvec(Lm, t0, up);
+    matvec(Lm, t1, um);
+    matvec(Lm, t2, dp);
+    matvec(Lm, t3, dm);
+    matvec(Lm, t4, dd);
+    const double bound = A.tvb_m * h * h;
+    double sc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const double mp = fabs(up[a]) <= bound ? up[a] : minmod3(up[a], dp[a], dm[a]);
+      const double mm = fabs(um[a]) <= bound ? um[a] : minmod3(um[a], dp[a], dm[a]);
+      troubled = troubled || (mp != up[a]) || (mm != um[a]);
+      sc[a] = minmod3(dd[a] / h, dp[a] / h, dm[a] / h);
+    }
+    matvec(Rm, sc, slope[ax]);
+  }
+
+  if (A.flags != nullptr) A.flags[e] = troubled ? 1 : 0;
+  if (!troubled) return;
+  if (A.count != nullptr) atomicAdd(A.count, 1);
+  const double hx = 0.5 * G.dx, hy = 0.5 * G.dy;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double* q = A.q + k * plane + (size_t)e * NSP;
+#pragma unroll
+    for (int j = 0; j < N1; ++j)
+#pragma unroll
+      for (int i = 0; i < N1; ++i)
+        q[j * N1 + i] = qb[k] + slope[0][k] * (hx * W.xi[i]) + slope[1][k] * (hy * W.xi[j]);
+  }
+}
+
+template <int P>
+static hipError_t launch_limit_t(const Geometry& g, const Tables1D& T, const LimitArgs& a,
+                                 hipStream_t s) {
+  const WTab<P + 1> w = make_wtab<P + 1>(T);
+  const int ne = g.nx * g.ny;
+  const dim3 grid((ne + 255) / 256), block(256);
+  hipLaunchKernelGGL((means_kernel<P>), grid, block, 0, s, g, w, a);
+  hipLaunchKernelGGL((limit_kernel<P>), grid, block, 0, s, g, w, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_limit(int P, const Geometry& g, const Tables1D& T, const LimitArgs& a,
+                        hipStream_t s) {
+  switch (P) {
+    case 1: return launch_limit_t<1>(g, T, a, s);
+    case 2: return launch_limit_t<2>(g, T, a, s);
+    case 3: return launch_limit_t<3>(g, T, a, s);
+    case 4: return launch_limit_t<4>(g, T, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------- reductions --
+constexpr int kRedBlock = 256;
+constexpr int kRedMaxBlocks = 1024;
+
+static int red_blocks(size_t npts) {
+  size_t b = (npts + kRedBlock - 1) / kRedBlock;
+  if (b > (size_t)kRedMaxBlocks) b = kRedMaxBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+size_t reduce_partials_size(int, const Geometry&) { return (size_t)kRedMaxBlocks * 4 + 8; }
+
+template <int P>
+__global__ __launch_bounds__(kRedBlock) void wavespeed_kernel(Geometry G, const double* q,
+                                                              unsigned long long* bits, int* err) {
+  constexpr int NSP = (P + 1) * (P + 1);
+  __shared__ double red[kRedBlock];
+  const size_t npts = (size_t)G.nx * G.ny * NSP;
+  double m = 0.0;
+  bool bad = false;
+  for (size_t g = blockIdx.x * (size_t)kRedBlock + threadIdx.x; g < npts;
+       g += (size_t)gridDim.x * kRedBlock) {
+    const double rho = q[g], mx = q[npts + g], my = q[2 * npts + g], en = q[3 * npts + g];
+    const double u = mx / rho, v = my / rho;
+    const double p = (G.gamma - 1.0) * (en - 0.5 * (mx * u + my * v));
+    bad = bad || !(rho > 0.0) || !(p > 0.0);
+    const double s = sqrt(u * u + v * v) + sqrt(G.gamma * p / rho);
+    if (s > m) m = s;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kRedBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(bits, (unsigned long long)__double_as_longlong(red[0]));
+  if (bad) atomicOr(err, 1);
+}
+
+hipError_t launch_max_wavespeed(int P, const Geometry& g, const double* q,
+                                unsigned long long* lam_bits, int* err, hipStream_t s) {
+  const size_t npts = (size_t)g.nx * g.ny * (P + 1) * (P + 1);
+  const dim3 grid(red_blocks(npts)), block(kRedBlock);
+  switch (P) {
+    case 1: hipLaunchKernelGGL((wavespeed_kernel<1>), grid, block, 0, s, g, q, lam_bits, err); break;
+    case 2: hipLaunchKernelGGL((wavespeed_kernel<2>), grid, block, 0, s, g, q, lam_bits, err); break;
+    case 3: hipLaunchKernelGGL((wavespeed_kernel<3>), grid, block, 0, s, g, q, lam_bits, err); break;
+    case 4: hipLaunchKernelGGL((wavespeed_kernel<4>), grid, block, 0, s, g, q, lam_bits, err); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ void cfl_dt_kernel(unsigned long long* bits, double cfl, double h, double t_end,
+                              double* t, double* dt, int* skip) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double lam = __longlong_as_double((long long)*bits);
+  *bits = 0ull;
+  const double tn = *t;
+  if (t_end > 0.0 && t_end - tn <= 1e-14 * t_end) {
+    *skip = 1;
+    *dt = 0.0;
+    return;
+  }
+  double d = cfl * h / lam;
+  if (t_end > 0.0 && d > t_end - tn) d = t_end - tn;
+  *dt = d;
+  *t = tn + d;
+  *skip = 0;
+}
+
+hipError_t launch_cfl_dt(unsigned long long* lam_bits, double cfl, double h, double t_end,
+                         double* t, double* dt, int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(cfl_dt_kernel, dim3(1), dim3(64), 0, s, lam_bits, cfl, h, t_end, t, dt, skip);
+  return hipGetLastError();
+}
+
+template <int P>
+__global__ __launch_bounds__(kRedBlock) void wsum_kernel(Geometry G, WTab<P + 1> W, int mode,
+                                                         const double* a, const double* b,
+                                                         int var, double* partials) {
+  constexpr int N1 = P + 1, NSP = N1 * N1;
+  __shared__ double red[4][kRedBlock];
+  const size_t npts = (size_t)G.nx * G.ny * NSP;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t g = blockIdx.x * (size_t)kRedBlock + threadIdx.x; g < npts;
+       g += (size_t)gridDim.x * kRedBlock) {
+    const int p = (int)(g % NSP);
+    const double w = W.w[p / N1] * W.w[p % N1];
+    if (mode == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[k] += w * a[k * npts + g];
+    } else {
+      const double d = a[var * npts + g] - (b != nullptr ? b[var * npts + g] : 0.0);
+      acc[0] += w * d * d;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = kRedBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) partials[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kRedBlock) void wsum_final_kernel(const double* partials, int nblocks,
+                                                               int mode, double scale, double area,
+                                                               double* out) {
+  __shared__ double red[4][kRedBlock];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kRedBlock)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += partials[b * 4 + k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = kRedBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (mode == 0) {
+      for (int k = 0; k < 4; ++k) out[k] = scale * red[k][0];
+    } else {
+      out[0] = sqrt(scale * red[0][0] / area);
+    }
+  }
+}
+
+hipError_t launch_weighted_sum(int P, const Geometry& g, const Tables1D& T, int mode,
+                               const double* a, const double* b, int var, double area,
+                               double* partials, double* out, hipStream_t s) {
+  const size_t npts = (size_t)g.nx * g.ny * (P + 1) * (P + 1);
+  const int nb = red_blocks(npts);
+  const dim3 grid(nb), block(kRedBlock);
+  switch (P) {
+    case 1: hipLaunchKernelGGL((wsum_kernel<1>), grid, block, 0, s, g, make_wtab<2>(T), mode, a, b, var, partials); break;
+    case 2: hipLaunchKernelGGL((wsum_kernel<2>), grid, block, 0, s, g, make_wtab<3>(T), mode, a, b, var, partials); break;
+    case 3: hipLaunchKernelGGL((wsum_kernel<3>), grid, block, 0, s, g, make_wtab<4>(T), mode, a, b, var, partials); break;
+    case 4: hipLaunchKernelGGL((wsum_kernel<4>), grid, block, 0, s, g, make_wtab<5>(T), mode, a, b, var, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  const double scale = 0.25 * g.dx * g.dy;
+  hipLaunchKernelGGL(wsum_final_kernel, dim3(1), dim3(kRedBlock), 0, s, partials, nb, mode, scale,
+                     area, out);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- helpers --
+template <int P>
+__global__ __launch_bounds__(256) void coords_kernel(Geometry G, WTab<P + 1> W, double x0,
+                                                     double y0, double* x, double* y) {
+  constexpr int N1 = P + 1, NSP = N1 * N1;
+  const size_t npts = (size_t)G.nx * G.ny * NSP;
+  const size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (g >= npts) return;
+  const size_t e = g / NSP;
+  const int p = (int)(g - e * NSP);
+  const int I = (int)(e % G.nx), J = (int)(e / G.nx);
+  x[g] = x0 + (I + 0.5) * G.dx + 0.5 * G.dx * W.xi[p % N1];
+  y[g] = y0 + (J + 0.5) * G.dy + 0.5 * G.dy * W.xi[p / N1];
+}
+
+hipError_t launch_coords(int P, const Geometry& g, const Tables1D& T, double x0, double y0,
+                         double* x, double* y, hipStream_t s) {
+  const size_t npts = (size_t)g.nx * g.ny * (P + 1) * (P + 1);
+  const dim3 grid((unsigned)((npts + 255) / 256)), block(256);
+  switch (P) {
+    case 1: hipLaunchKernelGGL((coords_kernel<1>), grid, block, 0, s, g, make_wtab<2>(T), x0, y0, x, y); break;
+    case 2: hipLaunchKernelGGL((coords_kernel<2>), grid, block, 0, s, g, make_wtab<3>(T), x0, y0, x, y); break;
+    case 3: hipLaunchKernelGGL((coords_kernel<3>), grid, block, 0, s, g, make_wtab<4>(T), x0, y0, x, y); break;
+    case 4: hipLaunchKernelGGL((coords_kernel<4>), grid, block, 0, s, g, make_wtab<5>(T), x0, y0, x, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int* p, int v, size_t n) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_int(int* p, int v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace cpr

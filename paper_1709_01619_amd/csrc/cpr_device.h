@@ -1,0 +1,120 @@
+// Device-side building blocks of the CPR kernels: compact tables, Euler
+// fluxes, the Rusanov face flux and the one-dimensional line operations
+// every sweep applies (extrapolation to both faces, flux evaluation,
+// derivative of the flux interpolant).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cpr_internal.h"
+
+namespace cpr {
+
+// Tables for N1 = P+1 points in the compute type R (kernel argument).
+template <typename R, int N1>
+struct KTab {
+  R D[N1][N1];
+  R em[N1], ep[N1], gL[N1], gR[N1];
+};
+
+template <typename R, int N1>
+inline KTab<R, N1> make_ktab(const Tables1D& T) {
+  KTab<R, N1> k;
+  for (int i = 0; i < N1; ++i) {
+    for (int l = 0; l < N1; ++l) k.D[i][l] = (R)T.D[i][l];
+    k.em[i] = (R)T.em[i];
+    k.ep[i] = (R)T.ep[i];
+    k.gL[i] = (R)T.gLp[i];
+    k.gR[i] = (R)T.gRp[i];
+  }
+  return k;
+}
+
+template <typename R>
+__device__ __forceinline__ R r_fma(R a, R b, R c) {
+  return fma(a, b, c);
+}
+
+// Fixed-order dot product used for every face extrapolation, so that the two
+// elements sharing a face compute bit-identical face states.
+template <int N1, typename R>
+__device__ __forceinline__ R dot_n(const R* c, const R* v) {
+  R s = c[0] * v[0];
+#pragma unroll
+  for (int n = 1; n < N1; ++n) s = r_fma(c[n], v[n], s);
+  return s;
+}
+
+// Flux of the Euler equations in direction AX (0: f, 1: g) at state q;
+// also returns the normal velocity, the pressure and 1/rho.
+template <int AX, typename R>
+__device__ __forceinline__ void euler_flux(const R q[4], R gm1, R F[4], R& un, R& p, R& ir) {
+  ir = R(1) / q[0];
+  un = q[1 + AX] * ir;
+  p = gm1 * (q[3] - R(0.5) * (q[1] * q[1] + q[2] * q[2]) * ir);
+  F[0] = q[1 + AX];
+  F[1] = q[1] * un;
+  F[2] = q[2] * un;
+  F[1 + AX] += p;
+  F[3] = un * (q[3] + p);
+}
+
+template <typename R>
+__device__ __forceinline__ bool nonphysical(R rho, R p) {
+  return !(rho > R(0)) || !(p > R(0));
+}
+
+// Rusanov flux across a face with normal +x (AX=0) or +y (AX=1):
+// 1/2 (F(qL) + F(qR)) - 1/2 lam (qR - qL), lam = max(|u_n| + c).
+template <int AX, typename R>
+__device__ __forceinline__ void rusanov(const R qL[4], const R qR[4], R gam, R gm1, R Fh[4],
+                                        bool& bad) {
+  R fL[4], fR[4], unL, pL, irL, unR, pR, irR;
+  euler_flux<AX>(qL, gm1, fL, unL, pL, irL);
+  euler_flux<AX>(qR, gm1, fR, unR, pR, irR);
+  const R lL = fabs(unL) + sqrt(gam * pL * irL);
+  const R lR = fabs(unR) + sqrt(gam * pR * irR);
+  const R lam = (lL >= lR) ? lL : lR;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Fh[k] = R(0.5) * (fL[k] + fR[k]) - R(0.5) * lam * (qR[k] - qL[k]);
+  bad = bad || nonphysical(qL[0], pL) || nonphysical(qR[0], pR);
+}
+
+// Line operations on the N1 points of one element row (AX=0) or column
+// (AX=1): face states qlo (at -1) and qhi (at +1), the flux interpolant's
+// face values flo, fhi, and its derivative dF at the points.
+template <int N1, int AX, typename R>
+__device__ __forceinline__ void line_ops(const R q[4][N1], const KTab<R, N1>& T, R gm1,
+                                         R qlo[4], R qhi[4], R flo[4], R fhi[4],
+                                         R dF[4][N1], bool& bad) {
+  R F[4][N1];
+#pragma unroll
+  for (int n = 0; n < N1; ++n) {
+    R qp[4] = {q[0][n], q[1][n], q[2][n], q[3][n]};
+    R fp[4], un, p, ir;
+    euler_flux<AX>(qp, gm1, fp, un, p, ir);
+    bad = bad || nonphysical(qp[0], p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) F[k][n] = fp[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    qlo[k] = dot_n<N1>(T.em, q[k]);
+    qhi[k] = dot_n<N1>(T.ep, q[k]);
+    flo[k] = dot_n<N1>(T.em, F[k]);
+    fhi[k] = dot_n<N1>(T.ep, F[k]);
+#pragma unroll
+    for (int i = 0; i < N1; ++i) dF[k][i] = dot_n<N1>(T.D[i], F[k]);
+  }
+}
+
+// XCD-aware tile order: consecutive dispatch slots go round-robin over the
+// 8 XCDs; give each XCD a contiguous range of tiles (raster order, x
+// fastest) so the halo rows shared by neighbouring tiles stay in one L2.
+__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+  const int xcd = bid & 7, k = bid >> 3;
+  const int per = ntiles >> 3, rem = ntiles & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+}  // namespace cpr

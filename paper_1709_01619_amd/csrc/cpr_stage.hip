@@ -1,0 +1,294 @@
+// Fused CPR residual + SSP-RK3 stage kernel for gfx950.
+//
+// One workgroup owns an 8x8 tile of elements and has 64*(P+1) lanes: wave w
+// works on line w of every element of the tile (row w in the x sweep, column
+// w in the y sweep), one element per lane. The residual of Section 2.2
+// (arXiv:1709.01619) splits into an x part that depends only on element rows
+// and a y part that depends only on element columns; each is a 1D CPR
+// operator along that line:
+//   R = -(2/dx)[D f + (F_W - f_W) gL' + (F_E - f_E) gR']      (rows)
+//       -(2/dy)[D g + (G_S - g_S) gL' + (G_N - g_N) gR']      (columns)
+// with face states extrapolated from each element's polynomial and the
+// Rusanov common flux (Section 4) at every face point.
+//
+// Phases of one workgroup:
+//  A  the tile (4 variables x 64 elements x (P+1)^2 float64) is copied into
+//     LDS with coalesced loads; lanes 0..32(P+1)-1 also load the line of the
+//     neighbouring element across the tile boundary that they own;
+//  B  those lanes finish the Rusanov flux on the tile-boundary faces; every
+//     lane reads its row and its column out of LDS;
+//  C  column sweep: interior face states travel between lanes by wave
+//     shuffles (neighbours along a column are adjacent lanes); the column
+//     residual is parked in LDS;
+//  D  row sweep the same way; the two parts are summed, the RK combination
+//     b (q_src + dt R) is formed in float64 and parked in LDS;
+//  E  coalesced epilogue q_dst = a q_n + (parked value).
+// Each tile-boundary face flux is computed by both tiles that share it from
+// bit-identical inputs, so the scheme stays exactly conservative.
+#include "cpr_device.h"
+
+namespace cpr {
+
+template <int P, typename R, int MODE>
+__global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R, P + 1> T,
+                                                             StageArgs A) {
+  constexpr int N1 = P + 1;
+  constexpr int NSP = N1 * N1;
+  constexpr int S = (NSP & 1) ? NSP : NSP + 1;  // odd LDS stride per element
+  constexpr int VS = 64 * S;                    // LDS stride per variable
+  constexpr int NT = 64 * N1;                   // lanes per workgroup
+  __shared__ double qs[4 * VS];
+  __shared__ R hF[4][kTile][N1][4];  // tile-boundary face fluxes: W, E, S, N
+
+  if (A.skip != nullptr && *A.skip != 0) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int tile = xcd_tile(blockIdx.x, G.ntx * G.nty);
+  const int tx = tile % G.ntx, ty = tile / G.ntx;
+  const int I0 = tx * kTile, J0 = ty * kTile;
+  const int nax = min(kTile, G.nx - I0), nay = min(kTile, G.ny - J0);
+  const size_t plane = (size_t)G.ny * G.nx * NSP;
+  const R gam = (R)G.gamma, gm1 = (R)(G.gamma - 1.0);
+  bool bad = false;
+
+  // ---- A: tile -> LDS (coalesced along each tile row of elements) ----
+  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
+    const int kr = d / (kTile * NSP);
+    const int r = d - kr * (kTile * NSP);
+    const int cx = r / NSP;
+    const int p = r - cx * NSP;
+    const int k = kr >> 3, cy = kr & 7;
+    if (cy < nay && cx < nax)
+      qs[k * VS + (cy * kTile + cx) * S + p] =
+          A.q_src[k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r];
+  }
+
+  // tile-boundary tasks: side hs (0 W, 1 E, 2 S, 3 N), position hp, line hm
+  const bool halo = tid < 4 * kTile * N1;
+  int hs = 0, hp = 0, hm = 0;
+  bool hact = false, hout = false;
+  R hq[4] = {R(0), R(0), R(0), R(0)};
+  if (halo) {
+    hs = tid / (kTile * N1);
+    const int r2 = tid - hs * (kTile * N1);
+    hp = r2 / N1;
+    hm = r2 - hp * N1;
+    int Io, Jo;
+    if (hs < 2) {
+      hact = hp < nay;
+      Jo = J0 + hp;
+      Io = (hs == 0) ? I0 - 1 : I0 + nax;
+    } else {
+      hact = hp < nax;
+      Io = I0 + hp;
+      Jo = (hs == 2) ? J0 - 1 : J0 + nay;
+    }
+    hout = true;
+    if (Io < 0 || Io >= G.nx) {
+      if (G.periodic) Io = (Io + G.nx) % G.nx; else hout = false;
+    }
+    if (Jo < 0 || Jo >= G.ny) {
+      if (G.periodic) Jo = (Jo + G.ny) % G.ny; else hout = false;
+    }
+    if (hact && hout) {
+      const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
+      R ln[4][N1];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int n = 0; n < N1; ++n)
+          ln[k][n] = (R)base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+      // the neighbour's face that touches this tile
+      const R* c = (hs == 0 || hs == 2) ? T.ep : T.em;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hq[k] = dot_n<N1>(c, ln[k]);
+    }
+  }
+  __syncthreads();
+
+  // ---- B: tile-boundary fluxes; every lane reads its row and column ----
+  if (halo && hact) {
+    int e, stride, off;
+    if (hs < 2) {  // row hm of element (0 or nax-1, hp)
+      e = hp * kTile + (hs == 0 ? 0 : nax - 1);
+      off = hm * N1;
+      stride = 1;
+    } else {  // column hm of element (hp, 0 or nay-1)
+      e = (hs == 2 ? 0 : nay - 1) * kTile + hp;
+      off = hm;
+      stride = N1;
+    }
+    R ln[4][N1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) ln[k][n] = (R)qs[k * VS + e * S + off + n * stride];
+    const R* c = (hs == 0 || hs == 2) ? T.em : T.ep;
+    R qin[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qin[k] = dot_n<N1>(c, ln[k]);
+    if (!hout) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hq[k] = qin[k];
+    }
+    const bool lo_side = (hs == 0 || hs == 2);  // neighbour is on the left/below
+    R qL[4], qR[4], Fh[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      qL[k] = lo_side ? hq[k] : qin[k];
+      qR[k] = lo_side ? qin[k] : hq[k];
+    }
+    if (hs < 2)
+      rusanov<0>(qL, qR, gam, gm1, Fh, bad);
+    else
+      rusanov<1>(qL, qR, gam, gm1, Fh, bad);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) hF[hs][hp][hm][k] = Fh[k];
+  }
+
+  // x sweep: lane -> element (cx = lane % 8, cy = lane / 8), row wv
+  // y sweep: lane -> element (cx = lane / 8, cy = lane % 8), column wv
+  const int cxX = lane & 7, cyX = lane >> 3, eX = lane;
+  const int cxY = lane >> 3, cyY = lane & 7, eY = cyY * kTile + cxY;
+  const bool actX = cxX < nax && cyX < nay;
+  const bool actY = cxY < nax && cyY < nay;
+  double qrow[4][N1];
+  R qcol[4][N1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
+      qcol[k][n] = (R)qs[k * VS + eY * S + n * N1 + wv];
+    }
+  __syncthreads();
+
+  const double dt = (A.dt_dev != nullptr) ? *A.dt_dev : A.dt;
+
+  // ---- C: column sweep ----
+  {
+    R qlo[4], qhi[4], flo[4], fhi[4], dF[4][N1];
+    bool b1 = false, b2 = false;
+    line_ops<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+    R qnb[4], Fs[4], Fn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], 1, 64);
+    rusanov<1>(qnb, qlo, gam, gm1, Fs, b2);
+    if (cyY == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fs[k] = hF[2][cxY][wv][k];
+      b2 = false;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Fn[k] = __shfl_down(Fs[k], 1, 64);
+    if (cyY == nay - 1) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fn[k] = hF[3][cxY][wv][k];
+    }
+    const R rd = (R)(-2.0 / G.dy);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) {
+        const R ry = rd * (dF[k][n] + (Fs[k] - flo[k]) * T.gL[n] + (Fn[k] - fhi[k]) * T.gR[n]);
+        qs[k * VS + eY * S + n * N1 + wv] = (double)ry;
+      }
+    if (actY) bad = bad || b1 || b2;
+  }
+
+  // ---- D: row sweep ----
+  R rx[4][N1];
+  {
+    R qr[4][N1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) qr[k][n] = (R)qrow[k][n];
+    R qlo[4], qhi[4], flo[4], fhi[4], dF[4][N1];
+    bool b1 = false, b2 = false;
+    line_ops<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+    R qnb[4], Fw[4], Fe[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], 1, 64);
+    rusanov<0>(qnb, qlo, gam, gm1, Fw, b2);
+    if (cxX == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fw[k] = hF[0][cyX][wv][k];
+      b2 = false;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Fe[k] = __shfl_down(Fw[k], 1, 64);
+    if (cxX == nax - 1) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fe[k] = hF[1][cyX][wv][k];
+    }
+    const R rd = (R)(-2.0 / G.dx);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n)
+        rx[k][n] = rd * (dF[k][n] + (Fw[k] - flo[k]) * T.gL[n] + (Fe[k] - fhi[k]) * T.gR[n]);
+    if (actX) bad = bad || b1 || b2;
+  }
+  __syncthreads();  // all column parts parked
+
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      const int a = k * VS + eX * S + wv * N1 + n;
+      const R rt = rx[k][n] + (R)qs[a];
+      if (MODE == kStageRK)
+        qs[a] = A.b * (qrow[k][n] + dt * (double)rt);
+      else
+        qs[a] = (double)rt;
+    }
+  __syncthreads();
+
+  // ---- E: coalesced epilogue ----
+  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
+    const int kr = d / (kTile * NSP);
+    const int r = d - kr * (kTile * NSP);
+    const int cx = r / NSP;
+    const int p = r - cx * NSP;
+    const int k = kr >> 3, cy = kr & 7;
+    if (cy < nay && cx < nax) {
+      const size_t g = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r;
+      const double v = qs[k * VS + (cy * kTile + cx) * S + p];
+      if (MODE == kStageRK) {
+        A.q_dst[g] = (A.a != 0.0) ? A.a * A.q_n[g] + v : v;
+      } else {
+        static_cast<R*>(A.r_out)[g] = (R)v;
+      }
+    }
+  }
+
+  if (bad) atomicOr(A.err, 1);
+}
+
+template <int P, typename R>
+static hipError_t launch_stage_t(int mode, const Geometry& g, const Tables1D& T,
+                                 const StageArgs& a, hipStream_t s) {
+  const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T);
+  const dim3 grid(g.ntx * g.nty), block(64 * (P + 1));
+  if (mode == kStageRK)
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageRK>), grid, block, 0, s, g, kt, a);
+  else
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageResidual>), grid, block, 0, s, g, kt, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(int P, bool fp32, int mode, const Geometry& g, const Tables1D& T,
+                        const StageArgs& a, hipStream_t s) {
+  switch (P) {
+    case 1: return fp32 ? launch_stage_t<1, float>(mode, g, T, a, s) : launch_stage_t<1, double>(mode, g, T, a, s);
+    case 2: return fp32 ? launch_stage_t<2, float>(mode, g, T, a, s) : launch_stage_t<2, double>(mode, g, T, a, s);
+    case 3: return fp32 ? launch_stage_t<3, float>(mode, g, T, a, s) : launch_stage_t<3, double>(mode, g, T, a, s);
+    case 4: return fp32 ? launch_stage_t<4, float>(mode, g, T, a, s) : launch_stage_t<4, double>(mode, g, T, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace cpr

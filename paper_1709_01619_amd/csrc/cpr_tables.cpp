@@ -1,0 +1,98 @@
+// Host construction of the 1D CPR tables for degree P (Section 2.2 of
+// arXiv:1709.01619: nodal solution polynomial of degree P, derivative of the
+// flux interpolant, Radau correction in the DG-equivalent form).
+//
+//  * Gauss-Legendre nodes by Newton's method on the Legendre three-term
+//    recurrence, weights 2 / ((1 - x^2) L'_{n}(x)^2).
+//  * Lagrange derivative matrix and face-extrapolation rows by the
+//    barycentric formulas (diagonal of D from the zero row sum).
+//  * Radau correction derivatives at the nodes from the DG equivalence of
+//    the Radau lift: gL'(xi_i) = -l_i(-1) / w_i, gR'(xi_i) = l_i(+1) / w_i.
+#include <cmath>
+
+#include "cpr_internal.h"
+
+namespace cpr {
+
+static void legendre_and_derivative(int n, double x, double* Ln, double* dLn) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    *Ln = 1.0;
+    *dLn = 0.0;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *Ln = p1;
+  *dLn = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+bool build_tables(int P, Tables1D* T) {
+  if (P < 1 || P > kMaxP) return false;
+  const int n = P + 1;
+  T->P = P;
+  for (int k = 0; k < n; ++k) {
+    // k-th root from the top, then stored in ascending order
+    double x = std::cos(M_PI * (k + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double L, dL;
+      legendre_and_derivative(n, x, &L, &dL);
+      double dx = L / dL;
+      x -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    double L, dL;
+    legendre_and_derivative(n, x, &L, &dL);
+    T->xi[n - 1 - k] = x;
+    T->w[n - 1 - k] = 2.0 / ((1.0 - x * x) * dL * dL);
+  }
+  // symmetrise (the rule is symmetric; removes one-ulp asymmetries)
+  for (int k = 0; k < n / 2; ++k) {
+    double a = 0.5 * (T->xi[n - 1 - k] - T->xi[k]);
+    T->xi[k] = -a;
+    T->xi[n - 1 - k] = a;
+    double wa = 0.5 * (T->w[k] + T->w[n - 1 - k]);
+    T->w[k] = T->w[n - 1 - k] = wa;
+  }
+  if (n % 2 == 1) T->xi[n / 2] = 0.0;
+
+  double bw[kMaxP + 1];
+  for (int l = 0; l < n; ++l) {
+    double prod = 1.0;
+    for (int m = 0; m < n; ++m)
+      if (m != l) prod *= (T->xi[l] - T->xi[m]);
+    bw[l] = 1.0 / prod;
+  }
+  for (int i = 0; i < n; ++i) {
+    double diag = 0.0;
+    for (int l = 0; l < n; ++l) {
+      if (l == i) continue;
+      double d = (bw[l] / bw[i]) / (T->xi[i] - T->xi[l]);
+      T->D[i][l] = d;
+      diag -= d;
+    }
+    T->D[i][i] = diag;
+  }
+  for (int side = 0; side < 2; ++side) {
+    const double x = side == 0 ? -1.0 : 1.0;
+    double den = 0.0;
+    for (int m = 0; m < n; ++m) den += bw[m] / (x - T->xi[m]);
+    for (int l = 0; l < n; ++l) {
+      double v = (bw[l] / (x - T->xi[l])) / den;
+      if (side == 0)
+        T->em[l] = v;
+      else
+        T->ep[l] = v;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    T->gLp[i] = -T->em[i] / T->w[i];
+    T->gRp[i] = T->ep[i] / T->w[i];
+  }
+  return true;
+}
+
+}  // namespace cpr

@@ -1,0 +1,397 @@
+// Discrete adjoint of the CPR residual: out = alpha v + delta J(q)^T v +
+// beta x + gam y, J = dR/dq of the float64 residual of cpr_stage.hip.
+//
+// Same tile and lane layout as the forward stage kernel: an 8x8 element
+// tile per workgroup, wave w on line w of every element. Each line is the
+// transpose of the forward 1D CPR operator along it. With a = -(2/h) v on
+// the line:
+//   sigma_lo = sum_i gL'_i a_i, sigma_hi = sum_i gR'_i a_i   (face flux cotangents)
+//   cot f_l  = sum_i D_il a_i - sigma_lo l_l(-1) - sigma_hi l_l(+1)
+//   cot q_l  = A(q_l)^T cot f_l + l_l(-1) cot q_lo + l_l(+1) cot q_hi
+// where the cotangent of a face flux is the sum of the sigmas of the two
+// elements sharing the face, pushed through the transposed Rusanov flux
+// (including the derivative of lam = max(|u_n| + c), d|u_n|/du_n = +1 at 0;
+// where the two one-sided speeds tie to 1e-12 relative, the gradient of max
+// is the mean of both sides' gradients). The two sides' contributions of an interior
+// face are exchanged between adjacent lanes by wave shuffles; tile-boundary
+// faces are finished by boundary lanes that read the neighbour element's line
+// of q and v from global memory. The paper (arXiv:1709.01619) has no
+// adjoint; this transposes its Section 2.2 residual operator.
+#include "cpr_device.h"
+
+namespace cpr {
+
+// (dF_AX/dq)^T s at state q.
+template <int AX>
+__device__ __forceinline__ void flux_jac_t(const double q[4], double gam, const double s[4],
+                                           double out[4]) {
+  constexpr int n = 1 + AX, t = 2 - AX;
+  const double ir = 1.0 / q[0];
+  const double un = q[n] * ir, ut = q[t] * ir;
+  const double gm1 = gam - 1.0;
+  const double ke = 0.5 * (un * un + ut * ut);
+  const double p = gm1 * (q[3] - q[0] * ke);
+  const double H = (q[3] + p) * ir;
+  const double phi = gm1 * ke;
+  out[0] = (phi - un * un) * s[n] - un * ut * s[t] + un * (phi - H) * s[3];
+  out[n] = s[0] + (3.0 - gam) * un * s[n] + ut * s[t] + (H - gm1 * un * un) * s[3];
+  out[t] = -gm1 * ut * s[n] + un * s[t] - gm1 * un * ut * s[3];
+  out[3] = gm1 * s[n] + gam * un * s[3];
+}
+
+// Gradient of |u_n| + c with respect to q.
+template <int AX>
+__device__ __forceinline__ void wave_speed_grad(const double q[4], double gam, double c,
+                                                double g[4]) {
+  constexpr int n = 1 + AX, t = 2 - AX;
+  const double ir = 1.0 / q[0];
+  const double un = q[n] * ir, ut = q[t] * ir;
+  const double gg = gam * (gam - 1.0);
+  const double sgn = un >= 0.0 ? 1.0 : -1.0;
+  const double i2c = 0.5 / c;
+  g[0] = gg * (-q[3] * ir * ir + (un * un + ut * ut) * ir) * i2c - sgn * un * ir;
+  g[n] = -gg * un * ir * i2c + sgn * ir;
+  g[t] = -gg * ut * ir * i2c;
+  g[3] = gg * ir * i2c;
+}
+
+// Cotangents of both face states of the Rusanov flux for output cotangent s.
+template <int AX>
+__device__ __forceinline__ void rusanov_vjp(const double qL[4], const double qR[4],
+                                            const double s[4], double gam, double cL[4],
+                                            double cR[4], bool& bad) {
+  constexpr int n = 1 + AX;
+  const double gm1 = gam - 1.0;
+  const double irL = 1.0 / qL[0], irR = 1.0 / qR[0];
+  const double pL = gm1 * (qL[3] - 0.5 * (qL[1] * qL[1] + qL[2] * qL[2]) * irL);
+  const double pR = gm1 * (qR[3] - 0.5 * (qR[1] * qR[1] + qR[2] * qR[2]) * irR);
+  const double cLs = sqrt(gam * pL * irL), cRs = sqrt(gam * pR * irR);
+  const double lL = fabs(qL[n] * irL) + cLs, lR = fabs(qR[n] * irR) + cRs;
+  const double lam = lL >= lR ? lL : lR;
+  const bool tie = fabs(lL - lR) <= 1e-12 * lam;
+  const double wl = tie ? 0.5 : (lL > lR ? 1.0 : 0.0);
+  const double wr = 1.0 - wl;
+  double jump = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) jump += s[k] * (qR[k] - qL[k]);
+  double aL[4], aR[4], gL[4], gR[4];
+  flux_jac_t<AX>(qL, gam, s, aL);
+  flux_jac_t<AX>(qR, gam, s, aR);
+  wave_speed_grad<AX>(qL, gam, cLs, gL);
+  wave_speed_grad<AX>(qR, gam, cRs, gR);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    cL[k] = 0.5 * aL[k] + 0.5 * lam * s[k] - 0.5 * jump * wl * gL[k];
+    cR[k] = 0.5 * aR[k] - 0.5 * lam * s[k] - 0.5 * jump * wr * gR[k];
+  }
+  bad = bad || nonphysical(qL[0], pL) || nonphysical(qR[0], pR);
+}
+
+template <int N1, int AX>
+struct LineAdj {
+  double qlo[4], qhi[4];  // face states
+  double slo[4], shi[4];  // own face flux cotangents (sigma)
+  double a[4][N1];        // -(2/h) v on the line
+};
+
+template <int N1, int AX>
+__device__ __forceinline__ void line_adj_prep(const double q[4][N1], const double v[4][N1],
+                                              const KTab<double, N1>& T, double rd,
+                                              LineAdj<N1, AX>& L) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int n = 0; n < N1; ++n) L.a[k][n] = rd * v[k][n];
+    L.qlo[k] = dot_n<N1>(T.em, q[k]);
+    L.qhi[k] = dot_n<N1>(T.ep, q[k]);
+    L.slo[k] = dot_n<N1>(T.gL, L.a[k]);
+    L.shi[k] = dot_n<N1>(T.gR, L.a[k]);
+  }
+}
+
+// cot q on the line from the face-state cotangents clo, chi.
+template <int N1, int AX>
+__device__ __forceinline__ void line_adj_finish(const double q[4][N1], const LineAdj<N1, AX>& L,
+                                                const double clo[4], const double chi[4],
+                                                const KTab<double, N1>& T, double gam,
+                                                double out[4][N1]) {
+#pragma unroll
+  for (int l = 0; l < N1; ++l) {
+    double cf[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) s += T.D[i][l] * L.a[k][i];
+      cf[k] = s - L.slo[k] * T.em[l] - L.shi[k] * T.ep[l];
+    }
+    const double qp[4] = {q[0][l], q[1][l], q[2][l], q[3][l]};
+    double jt[4];
+    flux_jac_t<AX>(qp, gam, cf, jt);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k][l] = jt[k] + T.em[l] * clo[k] + T.ep[l] * chi[k];
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<double, P + 1> T,
+                                                           VjpArgs A) {
+  constexpr int N1 = P + 1;
+  constexpr int NSP = N1 * N1;
+  constexpr int S = (NSP & 1) ? NSP : NSP + 1;
+  constexpr int VS = 64 * S;
+  constexpr int NT = 64 * N1;
+  __shared__ double qs[4 * VS];
+  __shared__ double vs[4 * VS];
+  __shared__ double hC[4][kTile][N1][4];  // inside face-state cotangents at tile boundaries
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int tile = xcd_tile(blockIdx.x, G.ntx * G.nty);
+  const int tx = tile % G.ntx, ty = tile / G.ntx;
+  const int I0 = tx * kTile, J0 = ty * kTile;
+  const int nax = min(kTile, G.nx - I0), nay = min(kTile, G.ny - J0);
+  const size_t plane = (size_t)G.ny * G.nx * NSP;
+  const double gam = G.gamma;
+  const double rdx = -2.0 / G.dx, rdy = -2.0 / G.dy;
+  bool bad = false;
+
+  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
+    const int kr = d / (kTile * NSP);
+    const int r = d - kr * (kTile * NSP);
+    const int cx = r / NSP;
+    const int p = r - cx * NSP;
+    const int k = kr >> 3, cy = kr & 7;
+    if (cy < nay && cx < nax) {
+      const size_t g = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r;
+      const int a = k * VS + (cy * kTile + cx) * S + p;
+      qs[a] = A.q[g];
+      vs[a] = A.v[g];
+    }
+  }
+
+  const bool halo = tid < 4 * kTile * N1;
+  int hs = 0, hp = 0, hm = 0;
+  bool hact = false, hout = false;
+  double oq[4] = {0, 0, 0, 0}, os[4] = {0, 0, 0, 0};
+  if (halo) {
+    hs = tid / (kTile * N1);
+    const int r2 = tid - hs * (kTile * N1);
+    hp = r2 / N1;
+    hm = r2 - hp * N1;
+    int Io, Jo;
+    if (hs < 2) {
+      hact = hp < nay;
+      Jo = J0 + hp;
+      Io = (hs == 0) ? I0 - 1 : I0 + nax;
+    } else {
+      hact = hp < nax;
+      Io = I0 + hp;
+      Jo = (hs == 2) ? J0 - 1 : J0 + nay;
+    }
+    hout = true;
+    if (Io < 0 || Io >= G.nx) {
+      if (G.periodic) Io = (Io + G.nx) % G.nx; else hout = false;
+    }
+    if (Jo < 0 || Jo >= G.ny) {
+      if (G.periodic) Jo = (Jo + G.ny) % G.ny; else hout = false;
+    }
+    if (hact && hout) {
+      const size_t base = ((size_t)Jo * G.nx + Io) * NSP;
+      double lq[4][N1], la[4][N1];
+      const double rd = hs < 2 ? rdx : rdy;
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int n = 0; n < N1; ++n) {
+          const size_t g = k * plane + base + (hs < 2 ? hm * N1 + n : n * N1 + hm);
+          lq[k][n] = A.q[g];
+          la[k][n] = rd * A.v[g];
+        }
+      // the outside element's face that touches this tile
+      const bool hi_face = (hs == 0 || hs == 2);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        oq[k] = dot_n<N1>(hi_face ? T.ep : T.em, lq[k]);
+        os[k] = dot_n<N1>(hi_face ? T.gR : T.gL, la[k]);
+      }
+    }
+  }
+  __syncthreads();
+
+  if (halo && hact) {
+    int e, stride, off;
+    if (hs < 2) {
+      e = hp * kTile + (hs == 0 ? 0 : nax - 1);
+      off = hm * N1;
+      stride = 1;
+    } else {
+      e = (hs == 2 ? 0 : nay - 1) * kTile + hp;
+      off = hm;
+      stride = N1;
+    }
+    const double rd = hs < 2 ? rdx : rdy;
+    double lq[4][N1], la[4][N1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) {
+        lq[k][n] = qs[k * VS + e * S + off + n * stride];
+        la[k][n] = rd * vs[k * VS + e * S + off + n * stride];
+      }
+    const bool lo_side = (hs == 0 || hs == 2);  // this tile's face is its low face
+    double iq[4], is[4], s[4], qL[4], qR[4], cL[4], cR[4], cin[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      iq[k] = dot_n<N1>(lo_side ? T.em : T.ep, lq[k]);
+      is[k] = dot_n<N1>(lo_side ? T.gL : T.gR, la[k]);
+      if (!hout) oq[k] = iq[k];
+      s[k] = hout ? is[k] + os[k] : is[k];
+      qL[k] = lo_side ? oq[k] : iq[k];
+      qR[k] = lo_side ? iq[k] : oq[k];
+    }
+    if (hs < 2)
+      rusanov_vjp<0>(qL, qR, s, gam, cL, cR, bad);
+    else
+      rusanov_vjp<1>(qL, qR, s, gam, cL, cR, bad);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // transmissive: both face states are the inside state
+      cin[k] = !hout ? cL[k] + cR[k] : (lo_side ? cR[k] : cL[k]);
+      hC[hs][hp][hm][k] = cin[k];
+    }
+  }
+
+  const int cxX = lane & 7, cyX = lane >> 3, eX = lane;
+  const int cxY = lane >> 3, cyY = lane & 7, eY = cyY * kTile + cxY;
+  const bool actX = cxX < nax && cyX < nay;
+  const bool actY = cxY < nax && cyY < nay;
+  double qrow[4][N1], vrow[4][N1], qcol[4][N1], vcol[4][N1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
+      vrow[k][n] = vs[k * VS + eX * S + wv * N1 + n];
+      qcol[k][n] = qs[k * VS + eY * S + n * N1 + wv];
+      vcol[k][n] = vs[k * VS + eY * S + n * N1 + wv];
+    }
+  __syncthreads();
+
+  // ---- column sweep (y) ----
+  {
+    LineAdj<N1, 1> L;
+    line_adj_prep<N1, 1>(qcol, vcol, T, rdy, L);
+    double qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      qnb[k] = __shfl_up(L.qhi[k], 1, 64);
+      snb[k] = __shfl_up(L.shi[k], 1, 64);
+      s[k] = L.slo[k] + snb[k];
+    }
+    bool b2 = false;
+    rusanov_vjp<1>(qnb, L.qlo, s, gam, cL, cR, b2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      clo[k] = cR[k];
+      chi[k] = __shfl_down(cL[k], 1, 64);
+    }
+    if (cyY == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) clo[k] = hC[2][cxY][wv][k];
+      b2 = false;
+    }
+    if (cyY == nay - 1) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) chi[k] = hC[3][cxY][wv][k];
+    }
+    double oc[4][N1];
+    line_adj_finish<N1, 1>(qcol, L, clo, chi, T, gam, oc);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = oc[k][n];
+    if (actY) bad = bad || b2;
+  }
+
+  // ---- row sweep (x) ----
+  double orow[4][N1];
+  {
+    LineAdj<N1, 0> L;
+    line_adj_prep<N1, 0>(qrow, vrow, T, rdx, L);
+    double qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      qnb[k] = __shfl_up(L.qhi[k], 1, 64);
+      snb[k] = __shfl_up(L.shi[k], 1, 64);
+      s[k] = L.slo[k] + snb[k];
+    }
+    bool b2 = false;
+    rusanov_vjp<0>(qnb, L.qlo, s, gam, cL, cR, b2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      clo[k] = cR[k];
+      chi[k] = __shfl_down(cL[k], 1, 64);
+    }
+    if (cxX == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) clo[k] = hC[0][cyX][wv][k];
+      b2 = false;
+    }
+    if (cxX == nax - 1) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) chi[k] = hC[1][cyX][wv][k];
+    }
+    line_adj_finish<N1, 0>(qrow, L, clo, chi, T, gam, orow);
+    if (actX) bad = bad || b2;
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      const int a = k * VS + eX * S + wv * N1 + n;
+      const double jt = orow[k][n] + qs[a];
+      qs[a] = A.alpha * vrow[k][n] + A.delta * jt;
+    }
+  __syncthreads();
+
+  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
+    const int kr = d / (kTile * NSP);
+    const int r = d - kr * (kTile * NSP);
+    const int cx = r / NSP;
+    const int p = r - cx * NSP;
+    const int k = kr >> 3, cy = kr & 7;
+    if (cy < nay && cx < nax) {
+      const size_t g = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r;
+      double o = qs[k * VS + (cy * kTile + cx) * S + p];
+      if (A.x != nullptr) o += A.beta * A.x[g];
+      if (A.y != nullptr) o += A.gam * A.y[g];
+      A.out[g] = o;
+    }
+  }
+  if (bad) atomicOr(A.err, 1);
+}
+
+template <int P>
+static hipError_t launch_vjp_t(const Geometry& g, const Tables1D& T, const VjpArgs& a,
+                               hipStream_t s) {
+  const KTab<double, P + 1> kt = make_ktab<double, P + 1>(T);
+  hipLaunchKernelGGL((vjp_kernel<P>), dim3(g.ntx * g.nty), dim3(64 * (P + 1)), 0, s, g, kt, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_vjp(int P, const Geometry& g, const Tables1D& T, const VjpArgs& a,
+                      hipStream_t s) {
+  switch (P) {
+    case 1: return launch_vjp_t<1>(g, T, a, s);
+    case 2: return launch_vjp_t<2>(g, T, a, s);
+    case 3: return launch_vjp_t<3>(g, T, a, s);
+    case 4: return launch_vjp_t<4>(g, T, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace cpr

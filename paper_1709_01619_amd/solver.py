@@ -1,0 +1,268 @@
+"""PyTorch-facing wrapper of the CPR library.
+
+torch supplies device memory and the stream; every computation runs in the
+HIP kernels of libcpr.so, reached through the C ABI (include/cpr.h). There is
+no fallback: constructing a Solver without the built library or without a
+GPU raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_double, c_int32, c_void_p
+
+import numpy as np
+
+from . import _lib
+
+BC = {"periodic": _lib.CPR_BC_PERIODIC, "transmissive": _lib.CPR_BC_TRANSMISSIVE}
+PRECISION = {"fp64": _lib.CPR_FP64, "fp32_bulk": _lib.CPR_FP32_BULK}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Solver:
+    """One CPR discretisation (degree P, mesh, boundary, precision, limiter)
+    bound to a GPU. States are float64 tensors of shape (4, ny, nx, P+1, P+1)
+    on that GPU (see include/cpr.h for the layout)."""
+
+    def __init__(self, P, nx, ny, x0=0.0, x1=10.0, y0=0.0, y1=10.0, bc="periodic",
+                 precision="fp64", gamma=1.4, limiter=False, tvb_m=10.0, cfl=0.0, t_end=0.0,
+                 device="cuda"):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("the CPR library needs a HIP (ROCm) GPU")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.P, self.nx, self.ny = int(P), int(nx), int(ny)
+        self.x0, self.x1, self.y0, self.y1 = float(x0), float(x1), float(y0), float(y1)
+        self.bc = bc
+        self.precision = precision
+        self.gamma = float(gamma)
+        self.limiter = bool(limiter)
+        cfg = _lib.make_config(self.P, self.nx, self.ny, self.x0, self.x1, self.y0, self.y1,
+                               BC[bc], PRECISION[precision], self.gamma,
+                               _lib.CPR_LIM_TVB_CHAR if limiter else _lib.CPR_LIM_NONE,
+                               float(tvb_m), float(cfl), float(t_end))
+        self._ctx = c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.cpr_init(byref(cfg), c_void_p(self._stream()), byref(self._ctx))
+        _lib.check(st, None, "cpr_init")
+
+    # ------------------------------------------------------------ plumbing --
+    def _stream(self):
+        torch = _torch()
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _enter(self):
+        self.lib.cpr_set_stream(self._ctx, c_void_p(self._stream()))
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self.lib.cpr_destroy(self._ctx)
+            self._ctx = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n1(self):
+        return self.P + 1
+
+    @property
+    def shape(self):
+        return (4, self.ny, self.nx, self.n1, self.n1)
+
+    @property
+    def n_unknowns(self):
+        return 4 * self.ny * self.nx * self.n1 * self.n1
+
+    @property
+    def dx(self):
+        return (self.x1 - self.x0) / self.nx
+
+    @property
+    def dy(self):
+        return (self.y1 - self.y0) / self.ny
+
+    def empty(self, dtype=None):
+        torch = _torch()
+        return torch.empty(self.shape, dtype=dtype or torch.float64, device=self.device)
+
+    def _ptr(self, t, dtype=None, shape=None, name="tensor"):
+        torch = _torch()
+        dtype = dtype or torch.float64
+        shape = shape or self.shape
+        if t.device != self.device:
+            raise ValueError(f"{name} must live on {self.device}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}")
+        if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor of shape {shape}")
+        return c_void_p(t.data_ptr())
+
+    def _check(self, st, what):
+        _lib.check(st, self._ctx, what)
+
+    # ------------------------------------------------------------- entries --
+    def residual(self, q, out=None):
+        torch = _torch()
+        rdt = torch.float32 if self.precision == "fp32_bulk" else torch.float64
+        if out is None:
+            out = self.empty(rdt)
+        self._enter()
+        self._check(self.lib.cpr_residual(self._ctx, self._ptr(q, name="q"),
+                                          self._ptr(out, rdt, name="r")), "cpr_residual")
+        return out
+
+    def step(self, q, dt, limit=False):
+        """One SSP-RK3 step in place; dt <= 0 uses the device CFL dt."""
+        self._enter()
+        self._check(self.lib.cpr_rk3_step(self._ctx, self._ptr(q, name="q"), float(dt),
+                                          1 if limit else 0), "cpr_rk3_step")
+        return q
+
+    def limit(self, q, flags=None, count=False):
+        torch = _torch()
+        self._enter()
+        fp = c_void_p(0)
+        if flags is not None:
+            fp = self._ptr(flags, torch.int32, (self.ny, self.nx), "flags")
+        n = c_int32(0)
+        self._check(self.lib.cpr_limit(self._ctx, self._ptr(q, name="q"), fp,
+                                       byref(n) if count else None), "cpr_limit")
+        return int(n.value) if count else None
+
+    def residual_vjp(self, q, v, out=None):
+        out = self.empty() if out is None else out
+        self._enter()
+        self._check(self.lib.cpr_residual_vjp(self._ctx, self._ptr(q, name="q"),
+                                              self._ptr(v, name="v"), self._ptr(out, name="out")),
+                    "cpr_residual_vjp")
+        return out
+
+    def adjoint_step(self, q_n, dt, lam_np1, out=None):
+        out = self.empty() if out is None else out
+        self._enter()
+        self._check(self.lib.cpr_adjoint_step(self._ctx, self._ptr(q_n, name="q_n"), float(dt),
+                                              self._ptr(lam_np1, name="lam_np1"),
+                                              self._ptr(out, name="lam_n")), "cpr_adjoint_step")
+        return out
+
+    def coords(self):
+        torch = _torch()
+        shp = (self.ny, self.nx, self.n1, self.n1)
+        x = torch.empty(shp, dtype=torch.float64, device=self.device)
+        y = torch.empty_like(x)
+        self._enter()
+        self._check(self.lib.cpr_point_coords(self._ctx, self._ptr(x, shape=shp),
+                                              self._ptr(y, shape=shp)), "cpr_point_coords")
+        return x, y
+
+    def integrals(self, q):
+        out = (c_double * 4)()
+        self._enter()
+        self._check(self.lib.cpr_integrals(self._ctx, self._ptr(q, name="q"), out), "cpr_integrals")
+        return np.array(out[:])
+
+    def l2_diff(self, a, b=None, var=0):
+        out = c_double(0.0)
+        self._enter()
+        bp = self._ptr(b, name="b") if b is not None else c_void_p(0)
+        self._check(self.lib.cpr_l2_diff(self._ctx, self._ptr(a, name="a"), bp, int(var),
+                                         byref(out)), "cpr_l2_diff")
+        return float(out.value)
+
+    def max_wavespeed(self, q):
+        out = c_double(0.0)
+        self._enter()
+        self._check(self.lib.cpr_max_wavespeed(self._ctx, self._ptr(q, name="q"), byref(out)),
+                    "cpr_max_wavespeed")
+        return float(out.value)
+
+    def set_time(self, t):
+        self._enter()
+        self._check(self.lib.cpr_set_time(self._ctx, float(t)), "cpr_set_time")
+
+    def get_time(self):
+        t, dt = c_double(0.0), c_double(0.0)
+        self._enter()
+        self._check(self.lib.cpr_get_time(self._ctx, byref(t), byref(dt)), "cpr_get_time")
+        return float(t.value), float(dt.value)
+
+    def sync(self):
+        self._enter()
+        self._check(self.lib.cpr_sync(self._ctx), "cpr_sync")
+
+    def quad_weights(self):
+        """w_i w_j dx dy / 4 per solution point, (n1, n1) float64 tensor,
+        from the library's own quadrature table."""
+        torch = _torch()
+        _, w, _, _ = _lib.tables(self.P)
+        w = torch.tensor(w, dtype=torch.float64, device=self.device)
+        return torch.outer(w, w) * (self.dx * self.dy / 4.0)
+
+
+class Rollout:
+    """nsteps unlimited SSP-RK3 steps of fixed dt as a differentiable map
+    q0 -> q_T (torch.autograd.Function). The backward pass runs the
+    hand-written discrete adjoint (cpr_adjoint_step) step by step in reverse,
+    storing the state every ckpt_every steps in the forward pass and
+    recomputing each segment's states before sweeping it backwards, so that
+    memory holds one segment plus the checkpoints."""
+
+    @staticmethod
+    def apply(q0, solver: Solver, dt: float, nsteps: int, ckpt_every: int):
+        return _rollout_fn().apply(q0, solver, float(dt), int(nsteps), int(ckpt_every))
+
+
+_ROLL = None
+
+
+def _rollout_fn():
+    global _ROLL
+    if _ROLL is not None:
+        return _ROLL
+    torch = _torch()
+
+    class _Rollout(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, q0, solver, dt, nsteps, ckpt_every):
+            if ckpt_every < 1 or nsteps < 0:
+                raise ValueError("need nsteps >= 0 and ckpt_every >= 1")
+            q = q0.detach().contiguous().clone()
+            ckpts = {0: q.clone()}
+            for n in range(nsteps):
+                solver.step(q, dt)
+                if (n + 1) % ckpt_every == 0 and n + 1 < nsteps:
+                    ckpts[n + 1] = q.clone()
+            ctx.solver, ctx.dt, ctx.nsteps, ctx.C, ctx.ckpts = solver, dt, nsteps, ckpt_every, ckpts
+            return q
+
+        @staticmethod
+        def backward(ctx, grad):
+            solver, dt, nsteps, C, ckpts = ctx.solver, ctx.dt, ctx.nsteps, ctx.C, ctx.ckpts
+            lam = grad.detach().contiguous().clone()
+            seg = torch.empty((min(C, max(nsteps, 1)),) + tuple(solver.shape), dtype=torch.float64,
+                              device=solver.device)
+            starts = list(range(0, nsteps, C))
+            for s0 in reversed(starts):
+                s1 = min(s0 + C, nsteps)
+                seg[0].copy_(ckpts[s0])
+                for n in range(s0 + 1, s1):
+                    seg[n - s0].copy_(seg[n - s0 - 1])
+                    solver.step(seg[n - s0], dt)
+                for n in range(s1 - 1, s0 - 1, -1):
+                    solver.adjoint_step(seg[n - s0], dt, lam, out=lam)
+            return lam, None, None, None, None
+
+    _ROLL = _Rollout
+    return _ROLL

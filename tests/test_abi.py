@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point include/cpr.h declares, rejects invalid configurations before touching
+the GPU, and its host table builder agrees with the oracle's tables."""
+
+import ctypes
+import os
+import re
+from ctypes import byref, c_void_p
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cpr.h")
+
+
+def _lib():
+    from paper_1709_01619_amd import _lib as L
+    try:
+        return L, L.load()
+    except ImportError as e:
+        pytest.fail(f"libcpr.so not built: {e}")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(cpr_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = header_functions()
+    for n in ("cpr_init", "cpr_residual", "cpr_rk3_step", "cpr_limit", "cpr_adjoint_step",
+              "cpr_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L, lib = _lib()
+    names = header_functions()
+    assert sorted(L.SYMBOLS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_config_struct_layout_matches_header():
+    L, _ = _lib()
+    # int32 x4, double x4, int32 x2, double, int32 x2, double x3
+    assert ctypes.sizeof(L.CprConfig) == 96
+    assert L.CprConfig.gamma.offset == 56
+    assert L.CprConfig.t_end.offset == 88
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 99), ("order_p", 0), ("order_p", 5), ("nx", 0), ("ny", -3),
+    ("x1", 0.0), ("y1", -1.0), ("bc", 7), ("precision", 3), ("gamma", 1.0),
+    ("gamma", float("nan")), ("limiter", 2), ("reserved0", 1), ("tvb_m", -1.0), ("cfl", -0.1),
+    ("t_end", float("inf")),
+])
+def test_init_rejects_invalid_config_without_gpu(field, value):
+    L, lib = _lib()
+    cfg = L.make_config(2, 4, 4)
+    setattr(cfg, field, value)
+    ctx = c_void_p()
+    assert lib.cpr_init(byref(cfg), None, byref(ctx)) == L.CPR_EINVAL
+    assert not ctx.value
+
+
+def test_null_arguments_rejected():
+    L, lib = _lib()
+    cfg = L.make_config(2, 4, 4)
+    assert lib.cpr_init(None, None, None) == L.CPR_EINVAL
+    assert lib.cpr_init(byref(cfg), None, None) == L.CPR_EINVAL
+    assert lib.cpr_residual(None, None, None) == L.CPR_EINVAL
+    assert lib.cpr_rk3_step(None, None, 0.1, 0) == L.CPR_EINVAL
+    assert lib.cpr_limit(None, None, None, None) == L.CPR_EINVAL
+    assert lib.cpr_adjoint_step(None, None, 0.1, None, None) == L.CPR_EINVAL
+    assert lib.cpr_destroy(None) == L.CPR_OK
+    assert lib.cpr_status_string(L.CPR_ENONPHYSICAL) == b"non-physical state"
+    assert lib.cpr_last_error(None) == b""
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_library_tables_agree_with_oracle(P):
+    """The library builds its tables by Newton iteration and barycentric
+    formulas, the oracle by numpy's Gauss-Legendre routine, Lagrange products
+    and Legendre-series derivatives; they agree to roundoff."""
+    L, lib = _lib()
+    from oracle import tables
+    xi, w, gl, gr = L.tables(P)
+    T = tables.get(P)
+    np.testing.assert_allclose(xi, T.xi, atol=2e-16)
+    np.testing.assert_allclose(w, T.w, atol=1e-15)
+    np.testing.assert_allclose(gl, T.gLp, atol=1e-13)
+    np.testing.assert_allclose(gr, T.gRp, atol=1e-13)
+    assert lib.cpr_tables(0, None, None, None, None) == L.CPR_EINVAL

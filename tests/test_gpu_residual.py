@@ -1,0 +1,170 @@
+"""GPU parity of the fused CPR residual / SSP-RK3 stage kernel against the
+oracle, element by element on seeded inputs.
+
+Tolerance (FP64): ||R_gpu - R_oracle||_inf <= 1e-12 max(1, ||R_oracle||_inf).
+Both evaluate the same formulas in float64 with different summation
+orders; the per-value rounding difference is a few ulps of the largest
+intermediate, (2/dx)(||D||_inf + 2||g'||_inf) max|F| ~ 1e2..1e3 times
+2.2e-16, far below the bound."""
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import cpr
+from tests.gpu_util import dev, host, make_solver, rel_err, say, torch
+
+pytestmark = pytest.mark.gpu
+
+MESHES = [(1, 1), (2, 2), (3, 5), (8, 8), (9, 8), (13, 11), (17, 3), (20, 20)]
+
+
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+@pytest.mark.parametrize("mesh", MESHES, ids=lambda m: f"{m[0]}x{m[1]}")
+def test_residual_fp64_matches_oracle(mesh, P, bc):
+    nx, ny = mesh
+    g = cpr.Grid(P=P, nx=nx, ny=ny, x0=0.0, x1=2.0, y0=-1.0, y1=0.5, bc=bc)
+    q = inputs.random_state((ny, nx, P + 1, P + 1), seed=1000 + 10 * P + nx)
+    say("residual fp64", P, nx, ny, bc)
+    R = cpr.residual(q, g)
+    s = make_solver(g)
+    Rg = host(s.residual(dev(q)))
+    assert rel_err(Rg, R) <= 1e-12
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_residual_bitwise_repeatable_and_conservative(P):
+    g = cpr.Grid(P=P, nx=19, ny=21, x0=0.0, x1=3.0, y0=0.0, y1=2.0, bc="periodic")
+    q = inputs.random_state((21, 19, P + 1, P + 1), seed=77 + P)
+    say("repeatable", P)
+    s = make_solver(g)
+    qd = dev(q)
+    r1 = host(s.residual(qd))
+    r2 = host(s.residual(qd))
+    assert np.array_equal(r1, r2)
+    # discrete conservation of the GPU residual (periodic)
+    tot = cpr.integrals(r1, g)
+    assert np.max(np.abs(tot)) < 1e-13 * np.max(np.abs(r1)) * 6.0
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_residual_fp32_bulk_error_bound(P):
+    """FP32-bulk residual against the FP64 oracle. Forward-error model:
+    each value carries a few float32 roundings of terms of size up to
+    (2/dx)(||D||_inf + 2||g'||_inf) max|F|; the test bound is 64 u32 times
+    that scale."""
+    from oracle import tables
+    g = cpr.Grid(P=P, nx=13, ny=9, x0=0.0, x1=2.0, y0=0.0, y1=1.0, bc="periodic")
+    q = inputs.random_state((9, 13, P + 1, P + 1), seed=500 + P)
+    say("residual fp32_bulk", P)
+    R = cpr.residual(q, g)
+    s = make_solver(g, precision="fp32_bulk")
+    Rg = host(s.residual(dev(q))).astype(np.float64)
+    T = tables.get(P)
+    normD = np.max(np.sum(np.abs(T.D), axis=1))
+    normg = max(np.max(np.abs(T.gLp)), np.max(np.abs(T.gRp)))
+    from oracle import euler
+    Fmax = max(np.max(np.abs(euler.flux_x(q, 1.4))), np.max(np.abs(euler.flux_y(q, 1.4))))
+    scale = 2.0 / min(g.dx, g.dy) * (normD + 2 * normg) * Fmax
+    err = np.max(np.abs(Rg - R))
+    print(f"fp32_bulk P={P}: max|dR| = {err:.3e}, scale*u32 = {scale * 2**-24:.3e}")
+    assert err <= 64 * 2.0 ** -24 * scale
+
+
+def test_nonphysical_state_reported():
+    from paper_1709_01619_amd import _lib
+    g = cpr.Grid(P=2, nx=9, ny=9, x1=1.0, y1=1.0)
+    q = inputs.random_state((9, 9, 3, 3), seed=3)
+    q[0, 4, 5, 1, 1] = -0.5
+    say("nonphysical")
+    s = make_solver(g)
+    s.residual(dev(q))
+    with pytest.raises(_lib.CprError) as ei:
+        s.sync()
+    assert ei.value.status == _lib.CPR_ENONPHYSICAL
+    s.sync()  # flag cleared
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_rk3_step_matches_oracle(P, bc):
+    g = cpr.Grid(P=P, nx=11, ny=10, x0=0.0, x1=10.0, y0=0.0, y1=10.0, bc=bc)
+    x, y = g.coords()
+    q = inputs.Vortex().conserved(x, y)
+    say("rk3 step", P, bc)
+    s = make_solver(g)
+    qd = dev(q)
+    dt = 0.01
+    q1 = q
+    for _ in range(3):
+        q1 = cpr.rk3_step(q1, dt, g)
+        s.step(qd, dt)
+    assert rel_err(host(qd), q1) <= 1e-12
+
+
+def test_small_vortex_config_100_steps():
+    """P=2, 20x20 periodic [0,10]^2, dt=1e-3, 100 steps, FP64: the GPU
+    state matches the oracle to 1e-12 and conserves the totals."""
+    g = cpr.Grid(P=2, nx=20, ny=20)
+    x, y = g.coords()
+    q0 = inputs.Vortex().conserved(x, y)
+    say("vortex 20x20 P2 100 steps")
+    qo = cpr.run(q0, g, 1e-3, 100)
+    s = make_solver(g)
+    qd = dev(q0)
+    for _ in range(100):
+        s.step(qd, 1e-3)
+    qg = host(qd)
+    assert np.max(np.abs(qg - qo)) <= 1e-12
+    I0 = cpr.integrals(q0, g)
+    Ig = s.integrals(qd)
+    assert np.max(np.abs(Ig - I0) / np.abs(I0)) < 1e-13
+
+
+@pytest.mark.parametrize("P", [2, 3])
+def test_device_cfl_dt_and_time_clipping(P):
+    g = cpr.Grid(P=P, nx=12, ny=12)
+    x, y = g.coords()
+    q0 = inputs.Vortex().conserved(x, y)
+    say("device dt", P)
+    cfl, t_end = 0.1, 0.05
+    s = make_solver(g, cfl=cfl, t_end=t_end)
+    s.set_time(0.0)
+    qd = dev(q0)
+    qo = q0
+    t = 0.0
+    for _ in range(200):
+        dt_o = min(cpr.cfl_dt(qo, g, cfl), t_end - t)
+        if t_end - t <= 1e-14 * t_end:
+            break
+        qo = cpr.rk3_step(qo, dt_o, g)
+        t += dt_o
+        s.step(qd, 0.0)
+        tg, dtg = s.get_time()
+        # the clipped last step t_end - t carries one ulp of t
+        assert abs(dtg - dt_o) <= 1e-14 * dt_o + 4 * np.spacing(t_end)
+    assert abs(t - t_end) < 1e-15
+    s.step(qd, 0.0)  # past t_end: no change
+    tg, _ = s.get_time()
+    assert abs(tg - t_end) < 1e-15
+    assert rel_err(host(qd), qo) <= 1e-12
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_reductions_match_oracle(P):
+    from oracle import euler
+    g = cpr.Grid(P=P, nx=23, ny=17, x0=-1.0, x1=2.0, y0=0.0, y1=1.5)
+    q = inputs.random_state((17, 23, P + 1, P + 1), seed=900 + P)
+    b = inputs.random_state((17, 23, P + 1, P + 1), seed=901 + P)
+    say("reductions", P)
+    s = make_solver(g)
+    qd, bd = dev(q), dev(b)
+    np.testing.assert_allclose(s.integrals(qd), cpr.integrals(q, g), rtol=1e-13)
+    for var in range(4):
+        assert abs(s.l2_diff(qd, bd, var) - cpr.l2_error(q[var], b[var], g)) <= 1e-13 * cpr.l2_error(q[var], b[var], g)
+    lam = float(np.max(euler.max_wave_speed(q, g.gamma)))
+    assert abs(s.max_wavespeed(qd) - lam) <= 1e-14 * lam
+    xg, yg = s.coords()
+    xo, yo = g.coords()
+    assert np.max(np.abs(host(xg) - xo)) < 1e-15 and np.max(np.abs(host(yg) - yo)) < 1e-15
