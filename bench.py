@@ -143,6 +143,36 @@ def cpu_baseline(P=3, n=256, steps=None, budget_s=15.0):
     }
 
 
+def profile_legs(a):
+    """Run selected legs only (used under rocprofv3): no JSON line."""
+    import torch
+    from paper_1709_01619_amd import Solver
+    legs = set(a.legs.split(","))
+    torch.cuda.init()
+    if "copy" in legs:
+        n = 1 << 27                      # 2^27 float64 = 1 GiB read + 1 GiB written
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copy: 3 x 1 GiB device-to-device copies", flush=True)
+    if "main" in legs:
+        for prec in ("fp64", "fp32_bulk"):
+            s = Solver(3, 256, 256, precision=prec)
+            q = vortex_state(s)
+            dt, _ = c2_dt(s, q)
+            ms = time_steps(s, q, dt, a.steps, a.warmup)
+            print(f"main P=3 256^2 {prec}: {ms:.4f} ms/step", flush=True)
+    if "scale" in legs:
+        for prec in ("fp64", "fp32_bulk"):
+            s = Solver(4, 1024, 1024, precision=prec)
+            q = vortex_state(s)
+            ms = time_steps(s, q, 1e-4, a.steps, a.warmup)
+            print(f"scale P=4 1024^2 {prec}: {ms:.4f} ms/step", flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,7 +181,13 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true",
                     help="skip the t=10 error runs, the adjoint and the P=4 legs")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of legs to run for profiling: main, l2, adjoint, scale, "
+                         "copy (a 1 GiB device copy that calibrates HBM byte counters); "
+                         "prints a short text report instead of the JSON line")
     a = ap.parse_args(argv)
+    if a.legs != "all":
+        return profile_legs(a)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU; the path has no multi-GPU mode "
               "(--gpus must be 1)", file=sys.stderr)
