@@ -6,7 +6,7 @@
 #include <cstring>
 #include <new>
 
-#include "../../include/cpr.h"
+#include "cpr.h"
 #include "cpr_internal.h"
 
 using namespace cpr;

@@ -35,6 +35,19 @@ __device__ __forceinline__ R r_fma(R a, R b, R c) {
   return fma(a, b, c);
 }
 
+// 1/x: the hardware reciprocal estimate refined by Newton's iteration
+// r <- r + r (1 - x r), which doubles the number of correct bits per step;
+// two steps take the float64 estimate to full precision (about 1 ulp). The
+// float32 estimate is already accurate to 1 ulp.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Fixed-order dot product used for every face extrapolation, so that the two
 // elements sharing a face compute bit-identical face states.
 template <int N1, typename R>
@@ -49,7 +62,7 @@ __device__ __forceinline__ R dot_n(const R* c, const R* v) {
 // also returns the normal velocity, the pressure and 1/rho.
 template <int AX, typename R>
 __device__ __forceinline__ void euler_flux(const R q[4], R gm1, R F[4], R& un, R& p, R& ir) {
-  ir = R(1) / q[0];
+  ir = recip(q[0]);
   un = q[1 + AX] * ir;
   p = gm1 * (q[3] - R(0.5) * (q[1] * q[1] + q[2] * q[2]) * ir);
   F[0] = q[1 + AX];
@@ -107,6 +120,31 @@ __device__ __forceinline__ void line_ops(const R q[4][N1], const KTab<R, N1>& T,
     for (int i = 0; i < N1; ++i) dF[k][i] = dot_n<N1>(T.D[i], F[k]);
   }
 }
+
+// Coalesced copy between one tile of a state (4 variables x kTile element
+// rows, each a contiguous run of nax*NSP float64 in global memory) and its
+// LDS image (element stride S). The 4*kTile runs are dealt to the N1 waves
+// of the workgroup (wave w takes runs w, w+N1, ...); within a run, lane l
+// of pass it handles value it*64+l. All loads of a wave are issued before
+// any of them is consumed, so one memory round trip covers the whole copy.
+template <int N1, int S>
+struct TileCopy {
+  static constexpr int NSP = N1 * N1;
+  static constexpr int SEG = kTile * NSP;          // values in a full run
+  static constexpr int NIT = (SEG + 63) / 64;      // passes per run
+  static constexpr int NRUN = (4 * kTile + N1 - 1) / N1;  // runs per wave
+  int loff[NIT];  // LDS offset, within its run, of the value a lane moves
+  __device__ __forceinline__ explicit TileCopy(int lane) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int f = it * 64 + lane;
+      const int cx = f / NSP;
+      loff[it] = cx * S + (f - cx * NSP);
+    }
+  }
+  // run u of wave wv: variable k, tile row cy; valid when sg < 4*kTile.
+  __device__ __forceinline__ static int run(int wv, int u) { return wv + N1 * u; }
+};
 
 // XCD-aware tile order: consecutive dispatch slots go round-robin over the
 // 8 XCDs; give each XCD a contiguous range of tiles (raster order, x

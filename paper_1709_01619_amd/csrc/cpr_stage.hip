@@ -30,13 +30,12 @@
 namespace cpr {
 
 template <int P, typename R, int MODE>
-__global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R, P + 1> T,
+__global__ __launch_bounds__(64 * (P + 1), 3) void stage_kernel(Geometry G, KTab<R, P + 1> T,
                                                              StageArgs A) {
   constexpr int N1 = P + 1;
   constexpr int NSP = N1 * N1;
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;  // odd LDS stride per element
   constexpr int VS = 64 * S;                    // LDS stride per variable
-  constexpr int NT = 64 * N1;                   // lanes per workgroup
   __shared__ double qs[4 * VS];
   __shared__ R hF[4][kTile][N1][4];  // tile-boundary face fluxes: W, E, S, N
 
@@ -54,15 +53,35 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
   bool bad = false;
 
   // ---- A: tile -> LDS (coalesced along each tile row of elements) ----
-  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
-    const int kr = d / (kTile * NSP);
-    const int r = d - kr * (kTile * NSP);
-    const int cx = r / NSP;
-    const int p = r - cx * NSP;
-    const int k = kr >> 3, cy = kr & 7;
-    if (cy < nay && cx < nax)
-      qs[k * VS + (cy * kTile + cx) * S + p] =
-          A.q_src[k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r];
+  using TC = TileCopy<N1, S>;
+  const TC tc(lane);
+  const int seg_len = nax * NSP;
+  {
+    double v[TC::NRUN][TC::NIT];
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const double* src = A.q_src + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        v[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      double* dst = qs + k * VS + cy * kTile * S;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) dst[tc.loff[it]] = v[u][it];
+      }
+    }
   }
 
   // tile-boundary tasks: side hs (0 W, 1 E, 2 S, 3 N), position hp, line hm
@@ -247,20 +266,40 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
     }
   __syncthreads();
 
-  // ---- E: coalesced epilogue ----
-  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
-    const int kr = d / (kTile * NSP);
-    const int r = d - kr * (kTile * NSP);
-    const int cx = r / NSP;
-    const int p = r - cx * NSP;
-    const int k = kr >> 3, cy = kr & 7;
-    if (cy < nay && cx < nax) {
-      const size_t g = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r;
-      const double v = qs[k * VS + (cy * kTile + cx) * S + p];
-      if (MODE == kStageRK) {
-        A.q_dst[g] = (A.a != 0.0) ? A.a * A.q_n[g] + v : v;
-      } else {
-        static_cast<R*>(A.r_out)[g] = (R)v;
+  // ---- E: coalesced epilogue (all q_n loads issued before the stores,
+  // which may overwrite q_n in place) ----
+  {
+    double vn[TC::NRUN][TC::NIT];
+    const bool need_qn = MODE == kStageRK && A.a != 0.0;
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = need_qn && sg < 4 * kTile && cy < nay;
+      const double* src = A.q_n + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        vn[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+      const double* img = qs + k * VS + cy * kTile * S;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) {
+          const double v = img[tc.loff[it]];
+          if (MODE == kStageRK)
+            A.q_dst[gb + f] = need_qn ? A.a * vn[u][it] + v : v;
+          else
+            static_cast<R*>(A.r_out)[gb + f] = (R)v;
+        }
       }
     }
   }
