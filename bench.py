@@ -36,6 +36,7 @@ METRIC = ("DOF-updates/s per RK stage (P=3, FP64 vs FP32-bulk) at fixed L2 error
           "adjoint s/step")
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNKNOWN_STEP = 64.0    # stage 1: 8 r + 8 w; stages 2, 3: 16 r + 8 w
+L2_MESHES = (32, 64, 128, 256)   # P=3 vortex to t=10; 64-256 are the workload's meshes
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "stage_kernel_counters_p3_256.md")
 
 
@@ -231,7 +232,7 @@ def main(argv=None):
         l2 = {}
         for prec in ("fp64", "fp32_bulk"):
             errs = []
-            for m in (64, 128, 256):
+            for m in L2_MESHES:
                 s = Solver(P, m, m, precision=prec)
                 q0 = vortex_state(s)
                 q = q0.clone()
@@ -243,8 +244,8 @@ def main(argv=None):
                 errs.append(e)
                 log(f"l2 {prec} {m}^2: {nst} steps, err {e:.4e}, {time.perf_counter() - t0:.2f} s")
                 del s, q, q0
-            orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
-            l2[prec] = {"meshes": [64, 128, 256], "l2_rho": errs, "observed_order": orders}
+            orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+            l2[prec] = {"meshes": list(L2_MESHES), "l2_rho": errs, "observed_order": orders}
 
     # ---- adjoint: P=3 128^2, 400 steps, dt=1e-3, checkpoint every 50 ----
     adj = None

@@ -37,6 +37,13 @@ def hipcc() -> str:
     return p
 
 
+# Files whose arithmetic must round exactly as written (the forward stage
+# and the limiter, which keep the scheme's x <-> y symmetry bit for bit):
+# floating-point contraction is off there and fused multiply-adds are
+# spelled out in the source.
+NO_CONTRACT = {"cpr_stage.hip", "cpr_aux.hip"}
+
+
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
                   if f.endswith((".hip", ".cpp")))
@@ -51,7 +58,8 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = False) -
     def compile_one(src):
         obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [cc, *COMMON, *opt, *lang, "-c", src, "-o", obj]
+        fp = ["-ffp-contract=off"] if os.path.basename(src) in NO_CONTRACT else []
+        cmd = [cc, *COMMON, *opt, *fp, *lang, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

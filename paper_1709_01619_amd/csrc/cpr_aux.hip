@@ -43,13 +43,14 @@ __global__ __launch_bounds__(256) void means_kernel(Geometry G, WTab<P + 1> W, L
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double* q = A.q + k * plane + (size_t)e * NSP;
+    // the (i,j) and (j,i) terms are added as a pair first, so that the mean
+    // of a transposed element is bitwise the same
     double s = 0.0;
 #pragma unroll
     for (int j = 0; j < N1; ++j) {
-      double r = 0.0;
+      s = fma(W.w[j] * W.w[j], q[j * N1 + j], s);
 #pragma unroll
-      for (int i = 0; i < N1; ++i) r += W.w[i] * q[j * N1 + i];
-      s += W.w[j] * r;
+      for (int i = j + 1; i < N1; ++i) s = fma(W.w[i] * W.w[j], q[j * N1 + i] + q[i * N1 + j], s);
     }
     A.qbar[k * ne + e] = 0.25 * s;
   }
@@ -61,7 +62,7 @@ template <int AX>
 __device__ void char_mats(const double qb[4], double gamma, double Rm[4][4], double Lm[4][4]) {
   const double rho = qb[0];
   const double u = qb[1] / rho, v = qb[2] / rho;
-  const double ke = 0.5 * (u * u + v * v);
+  const double ke = 0.5 * sym_dot2(u, u, v, v);
   const double p = (gamma - 1.0) * (qb[3] - rho * ke);
   const double c = sqrt(gamma * p / rho);
   const double H = (qb[3] + p) / rho;
@@ -96,9 +97,12 @@ __device__ __forceinline__ double minmod3(double a, double b, double c) {
   return pos ? m : (neg ? -m : 0.0);
 }
 
+// y = M x, summing the two momentum columns as a pair so that the x and y
+// directions of transposed data round identically.
 __device__ __forceinline__ void matvec(const double M[4][4], const double x[4], double y[4]) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a) y[a] = M[a][0] * x[0] + M[a][1] * x[1] + M[a][2] * x[2] + M[a][3] * x[3];
+  for (int a = 0; a < 4; ++a)
+    y[a] = fma(M[a][0], x[0], M[a][3] * x[3]) + sym_dot2(M[a][1], x[1], M[a][2], x[2]);
 }
 
 // ---------------------------------------------------- detect and limit --
@@ -130,15 +134,15 @@ __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, L
       double rw = 0.0, re = 0.0, cs = 0.0, cn = 0.0;
 #pragma unroll
       for (int i = 0; i < N1; ++i) {
-        rw += W.em[i] * q[j * N1 + i];   // row j extrapolated west
-        re += W.ep[i] * q[j * N1 + i];
-        cs += W.em[i] * q[i * N1 + j];   // column j extrapolated south
-        cn += W.ep[i] * q[i * N1 + j];
+        rw = fma(W.em[i], q[j * N1 + i], rw);  // row j extrapolated west
+        re = fma(W.ep[i], q[j * N1 + i], re);
+        cs = fma(W.em[i], q[i * N1 + j], cs);  // column j extrapolated south
+        cn = fma(W.ep[i], q[i * N1 + j], cn);
       }
-      w_ += W.w[j] * rw;
-      e_ += W.w[j] * re;
-      s_ += W.w[j] * cs;
-      n_ += W.w[j] * cn;
+      w_ = fma(W.w[j], rw, w_);
+      e_ = fma(W.w[j], re, e_);
+      s_ = fma(W.w[j], cs, s_);
+      n_ = fma(W.w[j], cn, n_);
     }
     fW[k] = 0.5 * w_;
     fE[k] = 0.5 * e_;
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, L
     for (int j = 0; j < N1; ++j)
 #pragma unroll
       for (int i = 0; i < N1; ++i)
-        q[j * N1 + i] = qb[k] + slope[0][k] * (hx * W.xi[i]) + slope[1][k] * (hy * W.xi[j]);
+        q[j * N1 + i] = qb[k] + sym_dot2(slope[0][k], hx * W.xi[i], slope[1][k], hy * W.xi[j]);
   }
 }
 
@@ -255,9 +259,9 @@ __global__ __launch_bounds__(kRedBlock) void wavespeed_kernel(Geometry G, const 
        g += (size_t)gridDim.x * kRedBlock) {
     const double rho = q[g], mx = q[npts + g], my = q[2 * npts + g], en = q[3 * npts + g];
     const double u = mx / rho, v = my / rho;
-    const double p = (G.gamma - 1.0) * (en - 0.5 * (mx * u + my * v));
+    const double p = (G.gamma - 1.0) * (en - 0.5 * sym_dot2(mx, u, my, v));
     bad = bad || !(rho > 0.0) || !(p > 0.0);
-    const double s = sqrt(u * u + v * v) + sqrt(G.gamma * p / rho);
+    const double s = sqrt(sym_dot2(u, u, v, v)) + sqrt(G.gamma * p / rho);
     if (s > m) m = s;
   }
   red[threadIdx.x] = m;

@@ -2,6 +2,11 @@
 // fluxes, the Rusanov face flux and the one-dimensional line operations
 // every sweep applies (extrapolation to both faces, flux evaluation,
 // derivative of the flux interpolant).
+//
+// The forward kernels are compiled without floating-point contraction and
+// spell every fused multiply-add out (r_fma), so each expression rounds
+// exactly as written and the x and y sweeps, which run the same code on
+// transposed data, round identically.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,6 +53,19 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// a*b + c*d rounded as two products and one sum, never fused: the result is
+// the same when the two pairs are swapped, which keeps every kernel's
+// rounding invariant under the x <-> y transposition of the data.
+__device__ __forceinline__ double sym_dot2(double a, double b, double c, double d) {
+  return __dadd_rn(__dmul_rn(a, b), __dmul_rn(c, d));
+}
+__device__ __forceinline__ float sym_dot2(float a, float b, float c, float d) {
+  return __fadd_rn(__fmul_rn(a, b), __fmul_rn(c, d));
+}
+
+__device__ __forceinline__ double sym_add(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float sym_add(float a, float b) { return __fadd_rn(a, b); }
+
 // Fixed-order dot product used for every face extrapolation, so that the two
 // elements sharing a face compute bit-identical face states.
 template <int N1, typename R>
@@ -64,11 +82,11 @@ template <int AX, typename R>
 __device__ __forceinline__ void euler_flux(const R q[4], R gm1, R F[4], R& un, R& p, R& ir) {
   ir = recip(q[0]);
   un = q[1 + AX] * ir;
-  p = gm1 * (q[3] - R(0.5) * (q[1] * q[1] + q[2] * q[2]) * ir);
+  p = gm1 * r_fma(-(R(0.5) * sym_dot2(q[1], q[1], q[2], q[2])), ir, q[3]);
   F[0] = q[1 + AX];
   F[1] = q[1] * un;
   F[2] = q[2] * un;
-  F[1 + AX] += p;
+  F[1 + AX] = r_fma(q[1 + AX], un, p);
   F[3] = un * (q[3] + p);
 }
 
@@ -89,7 +107,7 @@ __device__ __forceinline__ void rusanov(const R qL[4], const R qR[4], R gam, R g
   const R lR = fabs(unR) + sqrt(gam * pR * irR);
   const R lam = (lL >= lR) ? lL : lR;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) Fh[k] = R(0.5) * (fL[k] + fR[k]) - R(0.5) * lam * (qR[k] - qL[k]);
+  for (int k = 0; k < 4; ++k) Fh[k] = r_fma(-(R(0.5) * lam), qR[k] - qL[k], R(0.5) * (fL[k] + fR[k]));
   bad = bad || nonphysical(qL[0], pL) || nonphysical(qR[0], pR);
 }
 

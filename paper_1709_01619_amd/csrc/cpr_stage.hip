@@ -30,7 +30,7 @@
 namespace cpr {
 
 template <int P, typename R, int MODE>
-__global__ __launch_bounds__(64 * (P + 1), 3) void stage_kernel(Geometry G, KTab<R, P + 1> T,
+__global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R, P + 1> T,
                                                              StageArgs A) {
   constexpr int N1 = P + 1;
   constexpr int NSP = N1 * N1;
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(64 * (P + 1), 3) void stage_kernel(Geometry G, KTab
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int n = 0; n < N1; ++n) {
-        const R ry = rd * (dF[k][n] + (Fs[k] - flo[k]) * T.gL[n] + (Fn[k] - fhi[k]) * T.gR[n]);
+        const R ry = rd * r_fma(Fn[k] - fhi[k], T.gR[n], r_fma(Fs[k] - flo[k], T.gL[n], dF[k][n]));
         qs[k * VS + eY * S + n * N1 + wv] = (double)ry;
       }
     if (actY) bad = bad || b1 || b2;
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(64 * (P + 1), 3) void stage_kernel(Geometry G, KTab
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int n = 0; n < N1; ++n)
-        rx[k][n] = rd * (dF[k][n] + (Fw[k] - flo[k]) * T.gL[n] + (Fe[k] - fhi[k]) * T.gR[n]);
+        rx[k][n] = rd * r_fma(Fe[k] - fhi[k], T.gR[n], r_fma(Fw[k] - flo[k], T.gL[n], dF[k][n]));
     if (actX) bad = bad || b1 || b2;
   }
   __syncthreads();  // all column parts parked
@@ -258,9 +258,11 @@ __global__ __launch_bounds__(64 * (P + 1), 3) void stage_kernel(Geometry G, KTab
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
       const int a = k * VS + eX * S + wv * N1 + n;
-      const R rt = rx[k][n] + (R)qs[a];
+      // explicit rounding: a fused rx + ry would round the two sweeps'
+      // parts differently and break the x <-> y symmetry of the scheme
+      const R rt = sym_add(rx[k][n], (R)qs[a]);
       if (MODE == kStageRK)
-        qs[a] = A.b * (qrow[k][n] + dt * (double)rt);
+        qs[a] = A.b * fma(dt, (double)rt, qrow[k][n]);
       else
         qs[a] = (double)rt;
     }
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(64 * (P + 1), 3) void stage_kernel(Geometry G, KTab
         if (ok && f < seg_len) {
           const double v = img[tc.loff[it]];
           if (MODE == kStageRK)
-            A.q_dst[gb + f] = need_qn ? A.a * vn[u][it] + v : v;
+            A.q_dst[gb + f] = need_qn ? fma(A.a, vn[u][it], v) : v;
           else
             static_cast<R*>(A.r_out)[gb + f] = (R)v;
         }

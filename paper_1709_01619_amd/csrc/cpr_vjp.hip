@@ -140,7 +140,6 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   constexpr int NSP = N1 * N1;
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;
   constexpr int VS = 64 * S;
-  constexpr int NT = 64 * N1;
   __shared__ double qs[4 * VS];
   __shared__ double vs[4 * VS];
   __shared__ double hC[4][kTile][N1][4];  // inside face-state cotangents at tile boundaries
@@ -157,17 +156,39 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   const double rdx = -2.0 / G.dx, rdy = -2.0 / G.dy;
   bool bad = false;
 
-  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
-    const int kr = d / (kTile * NSP);
-    const int r = d - kr * (kTile * NSP);
-    const int cx = r / NSP;
-    const int p = r - cx * NSP;
-    const int k = kr >> 3, cy = kr & 7;
-    if (cy < nay && cx < nax) {
-      const size_t g = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r;
-      const int a = k * VS + (cy * kTile + cx) * S + p;
-      qs[a] = A.q[g];
-      vs[a] = A.v[g];
+  // tile of q and of v -> LDS; each wave issues all its loads of an array
+  // before writing any of them
+  using TC = TileCopy<N1, S>;
+  const TC tc(lane);
+  const int seg_len = nax * NSP;
+#pragma unroll
+  for (int arr = 0; arr < 2; ++arr) {
+    const double* gsrc = arr == 0 ? A.q : A.v;
+    double* lds = arr == 0 ? qs : vs;
+    double t[TC::NRUN][TC::NIT];
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const double* src = gsrc + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        t[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      double* dst = lds + k * VS + cy * kTile * S;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) dst[tc.loff[it]] = t[u][it];
+      }
     }
   }
 
@@ -358,18 +379,41 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
     }
   __syncthreads();
 
-  for (int d = tid; d < 4 * kTile * kTile * NSP; d += NT) {
-    const int kr = d / (kTile * NSP);
-    const int r = d - kr * (kTile * NSP);
-    const int cx = r / NSP;
-    const int p = r - cx * NSP;
-    const int k = kr >> 3, cy = kr & 7;
-    if (cy < nay && cx < nax) {
-      const size_t g = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP + r;
-      double o = qs[k * VS + (cy * kTile + cx) * S + p];
-      if (A.x != nullptr) o += A.beta * A.x[g];
-      if (A.y != nullptr) o += A.gam * A.y[g];
-      A.out[g] = o;
+  // epilogue: the x and y loads of a wave are issued before its stores
+  // (out may alias x)
+  {
+    double xv[TC::NRUN][TC::NIT], yv[TC::NRUN][TC::NIT];
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        const bool in = ok && f < seg_len;
+        xv[u][it] = (in && A.x != nullptr) ? A.x[gb + f] : 0.0;
+        yv[u][it] = (in && A.y != nullptr) ? A.y[gb + f] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+      const double* img = qs + k * VS + cy * kTile * S;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) {
+          double o = img[tc.loff[it]];
+          if (A.x != nullptr) o += A.beta * xv[u][it];
+          if (A.y != nullptr) o += A.gam * yv[u][it];
+          A.out[gb + f] = o;
+        }
+      }
     }
   }
   if (bad) atomicOr(A.err, 1);

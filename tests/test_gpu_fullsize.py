@@ -42,8 +42,8 @@ def _patch(q, g, I, J, r):
 
 
 def _fp32_scale(q, g):
-    """(2/h)(||D||_inf + 2||g'||_inf) max|F|: the size of the terms whose
-    float32 rounding the FP32-bulk residual carries."""
+    """(2/h)(||D||_inf + 2||g'||_inf) max|F|: the size of the terms the
+    residual is formed from (and whose rounding it carries)."""
     from oracle import euler, tables
     T = tables.get(g.P)
     normD = np.max(np.sum(np.abs(T.D), axis=1))
@@ -74,13 +74,17 @@ def test_fullsize_residual_sampled(P, n, prec):
     s = make_solver(g, precision=prec)
     R = host(s.residual(dev(q))).astype(np.float64)
     del s
-    bound32 = 64 * 2.0 ** -24 * _fp32_scale(q, g)
+    # the residual cancels terms of size scale = (2/h)(|D| + 2|g'|) max|F|;
+    # both sides round them in different orders
+    scale = _fp32_scale(q, g)
+    bound64 = 16 * 2.0 ** -53 * scale
+    bound32 = 64 * 2.0 ** -24 * scale
     for I, J in _samples(g, 24, seed=P * 100 + n):
         sub, pg, ci, cj = _patch(q, g, I, J, 1)
         Ro = cpr.residual(sub, pg)[:, cj, ci]
         Rg = R[:, J, I]
         if prec == "fp64":
-            assert np.max(np.abs(Rg - Ro)) <= 1e-12 * max(1.0, np.max(np.abs(Ro))), (I, J)
+            assert np.max(np.abs(Rg - Ro)) <= bound64, (I, J)
         else:
             # float32 forward-error scale of the residual (see test_gpu_residual)
             assert np.max(np.abs(Rg - Ro)) <= bound32, (I, J)
@@ -112,7 +116,7 @@ def test_fullsize_riemann_limited_run():
     """P=2 four-quadrant Riemann problem, 512x512 transmissive, TVB M=10,
     CFL 0.1 with the device dt, to t=0.3. Checks: the device time reaches
     t_end exactly, the state stays physical and finite, the solution keeps
-    the problem's diagonal symmetry, and the first limited step matches the
+    the problem's diagonal symmetry exactly, and the first limited step matches the
     oracle on sampled 13x13 patches (flags away from their thresholds)."""
     n = 512
     g = cpr.Grid(P=2, nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc="transmissive")
@@ -146,8 +150,10 @@ def test_fullsize_riemann_limited_run():
     rho = qT[0]
     from oracle import euler
     assert rho.min() > 0 and euler.pressure(qT, 1.4).min() > 0
+    # every kernel rounds transposed data identically, so the diagonal
+    # symmetry of the data survives 4600 limited steps bit for bit
     qt = qT[[0, 2, 1, 3]].transpose(0, 2, 1, 4, 3)
-    assert np.max(np.abs(qt - qT)) <= 1e-9 * np.max(np.abs(qT))
+    assert np.array_equal(qt, qT)
     print(f"riemann 512: {steps} steps to t=0.3, rho in [{rho.min():.4f}, {rho.max():.4f}]")
 
 

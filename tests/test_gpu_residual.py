@@ -168,3 +168,20 @@ def test_reductions_match_oracle(P):
     xg, yg = s.coords()
     xo, yo = g.coords()
     assert np.max(np.abs(host(xg) - xo)) < 1e-15 and np.max(np.abs(host(yg) - yo)) < 1e-15
+
+
+@pytest.mark.parametrize("P,prec", [(2, "fp64"), (3, "fp64"), (4, "fp64"), (3, "fp32_bulk")])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_residual_transpose_bitwise(P, prec, bc):
+    """The x and y sweeps round transposed data identically (no fused
+    multiply-add across a transposed pair), so the residual of the
+    transposed state is exactly the transposed residual. This also catches
+    any index mix-up between the two sweeps or the tile-boundary lanes."""
+    g = cpr.Grid(P=P, nx=21, ny=21, x0=0.0, x1=2.0, y0=0.0, y1=2.0, bc=bc)
+    q = inputs.random_state((21, 21, P + 1, P + 1), seed=600 + P)
+    qt = np.ascontiguousarray(q[[0, 2, 1, 3]].transpose(0, 2, 1, 4, 3))
+    say("transpose bitwise", P, prec, bc)
+    s = make_solver(g, precision=prec)
+    r = host(s.residual(dev(q)))
+    rt = host(s.residual(dev(qt)))
+    assert np.array_equal(rt, r[[0, 2, 1, 3]].transpose(0, 2, 1, 4, 3))
