@@ -15,22 +15,42 @@
 
 namespace cpr {
 
-// Tables for N1 = P+1 points in the compute type R (kernel argument).
+// Tables for N1 = P+1 points in the compute type R (kernel argument). The
+// Gauss points are symmetric about the element centre, so the tables are
+// too: D[N1-1-i][N1-1-l] = -D[i][l], l_l(+1) = l_{N1-1-l}(-1) and
+// gR'(xi_i) = -gL'(xi_{N1-1-i}); the host tables hold these identities
+// exactly. Only the independent half is passed (rows i <= N1/2 of D, with
+// the centre row's own symmetry, l(-1) and gL'), which halves the scalar
+// registers the tables occupy; the accessors rebuild every entry by an
+// exact negation or index mirror.
 template <typename R, int N1>
 struct KTab {
-  R D[N1][N1];
-  R em[N1], ep[N1], gL[N1], gR[N1];
+  static constexpr int H = (N1 + 1) / 2;  // rows kept; row H-1 is the centre row for odd N1
+  R Dh[H][N1];
+  R em_[N1];
+  R gL_[N1];
+  __device__ __forceinline__ R D(int i, int l) const {
+    if (i < N1 - 1 - i) return Dh[i][l];
+    if (i > N1 - 1 - i) return -Dh[N1 - 1 - i][N1 - 1 - l];
+    // centre row of an odd rule: antisymmetric about the centre, zero there
+    if (l < N1 - 1 - l) return Dh[i][l];
+    if (l > N1 - 1 - l) return -Dh[i][N1 - 1 - l];
+    return R(0);
+  }
+  __device__ __forceinline__ R em(int l) const { return em_[l]; }
+  __device__ __forceinline__ R ep(int l) const { return em_[N1 - 1 - l]; }
+  __device__ __forceinline__ R gL(int i) const { return gL_[i]; }
+  __device__ __forceinline__ R gR(int i) const { return -gL_[N1 - 1 - i]; }
 };
 
 template <typename R, int N1>
 inline KTab<R, N1> make_ktab(const Tables1D& T) {
   KTab<R, N1> k;
+  for (int i = 0; i < KTab<R, N1>::H; ++i)
+    for (int l = 0; l < N1; ++l) k.Dh[i][l] = (R)T.D[i][l];
   for (int i = 0; i < N1; ++i) {
-    for (int l = 0; l < N1; ++l) k.D[i][l] = (R)T.D[i][l];
-    k.em[i] = (R)T.em[i];
-    k.ep[i] = (R)T.ep[i];
-    k.gL[i] = (R)T.gLp[i];
-    k.gR[i] = (R)T.gRp[i];
+    k.em_[i] = (R)T.em[i];
+    k.gL_[i] = (R)T.gLp[i];
   }
   return k;
 }
@@ -68,11 +88,11 @@ __device__ __forceinline__ float sym_add(float a, float b) { return __fadd_rn(a,
 
 // Fixed-order dot product used for every face extrapolation, so that the two
 // elements sharing a face compute bit-identical face states.
-template <int N1, typename R>
-__device__ __forceinline__ R dot_n(const R* c, const R* v) {
-  R s = c[0] * v[0];
+template <int N1, typename R, typename C>
+__device__ __forceinline__ R dot_n(C c, const R* v) {
+  R s = c(0) * v[0];
 #pragma unroll
-  for (int n = 1; n < N1; ++n) s = r_fma(c[n], v[n], s);
+  for (int n = 1; n < N1; ++n) s = r_fma(c(n), v[n], s);
   return s;
 }
 
@@ -130,12 +150,12 @@ __device__ __forceinline__ void line_ops(const R q[4][N1], const KTab<R, N1>& T,
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    qlo[k] = dot_n<N1>(T.em, q[k]);
-    qhi[k] = dot_n<N1>(T.ep, q[k]);
-    flo[k] = dot_n<N1>(T.em, F[k]);
-    fhi[k] = dot_n<N1>(T.ep, F[k]);
+    qlo[k] = dot_n<N1>([&](int n) { return T.em(n); }, q[k]);
+    qhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, q[k]);
+    flo[k] = dot_n<N1>([&](int n) { return T.em(n); }, F[k]);
+    fhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, F[k]);
 #pragma unroll
-    for (int i = 0; i < N1; ++i) dF[k][i] = dot_n<N1>(T.D[i], F[k]);
+    for (int i = 0; i < N1; ++i) dF[k][i] = dot_n<N1>([&](int n) { return T.D(i, n); }, F[k]);
   }
 }
 

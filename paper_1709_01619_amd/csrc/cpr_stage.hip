@@ -1,8 +1,8 @@
 // Fused CPR residual + SSP-RK3 stage kernel for gfx950.
 //
-// One workgroup owns an 8x8 tile of elements and has 64*(P+1) lanes: wave w
-// works on line w of every element of the tile (row w in the x sweep, column
-// w in the y sweep), one element per lane. The residual of Section 2.2
+// A tile of 8x8 elements is worked on by 64*(P+1) lanes: wave w works on
+// line w of every element of the tile (row w in the x sweep, column w in
+// the y sweep), one element per lane. The residual of Section 2.2
 // (arXiv:1709.01619) splits into an x part that depends only on element rows
 // and a y part that depends only on element columns; each is a 1D CPR
 // operator along that line:
@@ -11,51 +11,84 @@
 // with face states extrapolated from each element's polynomial and the
 // Rusanov common flux (Section 4) at every face point.
 //
-// Phases of one workgroup:
+// A workgroup holds TPW tiles side by side; the tiles share only the
+// barriers. With P = 4 in float64 a one-tile workgroup has 5 waves and
+// needs more than 128 VGPRs per lane, and a CU then hosts only one such
+// workgroup at a time; a two-tile workgroup (10 waves) keeps two tiles in
+// flight per CU.
+//
+// Phases of one tile:
 //  A  the tile (4 variables x 64 elements x (P+1)^2 float64) is copied into
 //     LDS with coalesced loads; lanes 0..32(P+1)-1 also load the line of the
-//     neighbouring element across the tile boundary that they own;
+//     neighbouring element across the tile boundary that they own. All of
+//     a wave's loads are issued before any is used: one memory round trip;
 //  B  those lanes finish the Rusanov flux on the tile-boundary faces; every
-//     lane reads its row and its column out of LDS;
+//     lane reads its column out of LDS;
 //  C  column sweep: interior face states travel between lanes by wave
-//     shuffles (neighbours along a column are adjacent lanes); the column
-//     residual is parked in LDS;
-//  D  row sweep the same way; the two parts are summed, the RK combination
-//     b (q_src + dt R) is formed in float64 and parked in LDS;
+//     shuffles (neighbours along a column are adjacent lanes). The column
+//     residual stays in registers until every lane has read its row, then
+//     replaces the tile image in LDS;
+//  D  row sweep the same way; this tile's q_n loads are issued, then the two
+//     parts are summed and the RK combination b (q_src + dt R) is formed in
+//     float64 and parked in LDS;
 //  E  coalesced epilogue q_dst = a q_n + (parked value).
-// Each tile-boundary face flux is computed by both tiles that share it from
+// Each line is held in registers only during its own sweep, which keeps the
+// register peak low enough for several workgroups per CU. Each
+// tile-boundary face flux is computed by both tiles that share it from
 // bit-identical inputs, so the scheme stays exactly conservative.
 #include "cpr_device.h"
 
 namespace cpr {
 
+template <int N1, typename R>
+struct TilesPerGroup {
+  static constexpr int value = (N1 == 5 && sizeof(R) == 8) ? 2 : 1;
+};
+
 template <int P, typename R, int MODE>
-__global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R, P + 1> T,
-                                                             StageArgs A) {
+__global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) void stage_kernel(
+    Geometry G, KTab<R, P + 1> T, StageArgs A) {
   constexpr int N1 = P + 1;
   constexpr int NSP = N1 * N1;
+  constexpr int TPW = TilesPerGroup<N1, R>::value;
+  constexpr int NT = 64 * N1;                   // lanes per tile
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;  // odd LDS stride per element
   constexpr int VS = 64 * S;                    // LDS stride per variable
-  __shared__ double qs[4 * VS];
-  __shared__ R hF[4][kTile][N1][4];  // tile-boundary face fluxes: W, E, S, N
+  __shared__ double qs_all[TPW][4 * VS];
+  __shared__ R hF_all[TPW][4][kTile][N1][4];  // tile-boundary face fluxes: W, E, S, N
 
   if (A.skip != nullptr && *A.skip != 0) return;
 
-  const int tid = threadIdx.x;
+  // tile of this group of waves; wave-uniform values live in scalar registers
+  const int slot = TPW == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x / NT);
+  const int tid = (int)threadIdx.x - slot * NT;
   const int lane = tid & 63;
-  const int wv = tid >> 6;
-  const int tile = xcd_tile(blockIdx.x, G.ntx * G.nty);
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ntiles = G.ntx * G.nty;
+  const int tile = xcd_tile(blockIdx.x, (ntiles + TPW - 1) / TPW) * TPW + slot;
+  const bool live = tile < ntiles;  // the last group's trailing slots may be empty
   const int tx = tile % G.ntx, ty = tile / G.ntx;
   const int I0 = tx * kTile, J0 = ty * kTile;
-  const int nax = min(kTile, G.nx - I0), nay = min(kTile, G.ny - J0);
+  const int nax = live ? min(kTile, G.nx - I0) : 0;
+  const int nay = live ? min(kTile, G.ny - J0) : 0;
   const size_t plane = (size_t)G.ny * G.nx * NSP;
   const R gam = (R)G.gamma, gm1 = (R)(G.gamma - 1.0);
+  double* qs = qs_all[slot];
+  auto hF = hF_all[slot];
   bool bad = false;
 
-  // ---- A: tile -> LDS (coalesced along each tile row of elements) ----
   using TC = TileCopy<N1, S>;
   const TC tc(lane);
   const int seg_len = nax * NSP;
+
+  // tile-boundary tasks: side hs (0 W, 1 E, 2 S, 3 N), position hp, line hm
+  const bool halo = tid < 4 * kTile * N1;
+  int hs = 0, hp = 0, hm = 0;
+  bool hact = false, hout = false;
+  R hq[4] = {R(0), R(0), R(0), R(0)};
+
+  // ---- A: tile -> LDS (coalesced along each tile row of elements) and the
+  // outside neighbour lines, all loads issued before any is consumed ----
   {
     double v[TC::NRUN][TC::NIT];
 #pragma unroll
@@ -70,6 +103,38 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
         v[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
       }
     }
+    double hraw[4][N1];
+    if (halo) {
+      hs = tid / (kTile * N1);
+      const int r2 = tid - hs * (kTile * N1);
+      hp = r2 / N1;
+      hm = r2 - hp * N1;
+      int Io, Jo;
+      if (hs < 2) {
+        hact = hp < nay;
+        Jo = J0 + hp;
+        Io = (hs == 0) ? I0 - 1 : I0 + nax;
+      } else {
+        hact = hp < nax;
+        Io = I0 + hp;
+        Jo = (hs == 2) ? J0 - 1 : J0 + nay;
+      }
+      hout = true;
+      if (Io < 0 || Io >= G.nx) {
+        if (G.periodic) Io = (Io + G.nx) % G.nx; else hout = false;
+      }
+      if (Jo < 0 || Jo >= G.ny) {
+        if (G.periodic) Jo = (Jo + G.ny) % G.ny; else hout = false;
+      }
+      if (hact && hout) {
+        const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int n = 0; n < N1; ++n)
+            hraw[k][n] = base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < TC::NRUN; ++u) {
       const int sg = TC::run(wv, u);
@@ -82,52 +147,22 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
         if (ok && f < seg_len) dst[tc.loff[it]] = v[u][it];
       }
     }
-  }
-
-  // tile-boundary tasks: side hs (0 W, 1 E, 2 S, 3 N), position hp, line hm
-  const bool halo = tid < 4 * kTile * N1;
-  int hs = 0, hp = 0, hm = 0;
-  bool hact = false, hout = false;
-  R hq[4] = {R(0), R(0), R(0), R(0)};
-  if (halo) {
-    hs = tid / (kTile * N1);
-    const int r2 = tid - hs * (kTile * N1);
-    hp = r2 / N1;
-    hm = r2 - hp * N1;
-    int Io, Jo;
-    if (hs < 2) {
-      hact = hp < nay;
-      Jo = J0 + hp;
-      Io = (hs == 0) ? I0 - 1 : I0 + nax;
-    } else {
-      hact = hp < nax;
-      Io = I0 + hp;
-      Jo = (hs == 2) ? J0 - 1 : J0 + nay;
-    }
-    hout = true;
-    if (Io < 0 || Io >= G.nx) {
-      if (G.periodic) Io = (Io + G.nx) % G.nx; else hout = false;
-    }
-    if (Jo < 0 || Jo >= G.ny) {
-      if (G.periodic) Jo = (Jo + G.ny) % G.ny; else hout = false;
-    }
-    if (hact && hout) {
-      const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
+    if (halo && hact && hout) {
       R ln[4][N1];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int n = 0; n < N1; ++n)
-          ln[k][n] = (R)base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+        for (int n = 0; n < N1; ++n) ln[k][n] = (R)hraw[k][n];
       // the neighbour's face that touches this tile
-      const R* c = (hs == 0 || hs == 2) ? T.ep : T.em;
+      const bool hi = (hs == 0 || hs == 2);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) hq[k] = dot_n<N1>(c, ln[k]);
+      for (int k = 0; k < 4; ++k)
+        hq[k] = dot_n<N1>([&](int n) { return hi ? T.ep(n) : T.em(n); }, ln[k]);
     }
   }
   __syncthreads();
 
-  // ---- B: tile-boundary fluxes; every lane reads its row and column ----
+  // ---- B: tile-boundary fluxes; every lane reads its column ----
   if (halo && hact) {
     int e, stride, off;
     if (hs < 2) {  // row hm of element (0 or nax-1, hp)
@@ -144,10 +179,11 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int n = 0; n < N1; ++n) ln[k][n] = (R)qs[k * VS + e * S + off + n * stride];
-    const R* c = (hs == 0 || hs == 2) ? T.em : T.ep;
+    const bool lo = (hs == 0 || hs == 2);
     R qin[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) qin[k] = dot_n<N1>(c, ln[k]);
+    for (int k = 0; k < 4; ++k)
+      qin[k] = dot_n<N1>([&](int n) { return lo ? T.em(n) : T.ep(n); }, ln[k]);
     if (!hout) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) hq[k] = qin[k];
@@ -173,20 +209,17 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
   const int cxY = lane >> 3, cyY = lane & 7, eY = cyY * kTile + cxY;
   const bool actX = cxX < nax && cyX < nay;
   const bool actY = cxY < nax && cyY < nay;
-  double qrow[4][N1];
   R qcol[4][N1];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int n = 0; n < N1; ++n) {
-      qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
-      qcol[k][n] = (R)qs[k * VS + eY * S + n * N1 + wv];
-    }
-  __syncthreads();
+    for (int n = 0; n < N1; ++n) qcol[k][n] = (R)qs[k * VS + eY * S + n * N1 + wv];
+  __syncthreads();  // tile-boundary fluxes are in hF
 
   const double dt = (A.dt_dev != nullptr) ? *A.dt_dev : A.dt;
 
   // ---- C: column sweep ----
+  R ry[4][N1];
   {
     R qlo[4], qhi[4], flo[4], fhi[4], dF[4][N1];
     bool b1 = false, b2 = false;
@@ -210,12 +243,21 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
-      for (int n = 0; n < N1; ++n) {
-        const R ry = rd * r_fma(Fn[k] - fhi[k], T.gR[n], r_fma(Fs[k] - flo[k], T.gL[n], dF[k][n]));
-        qs[k * VS + eY * S + n * N1 + wv] = (double)ry;
-      }
+      for (int n = 0; n < N1; ++n)
+        ry[k][n] = rd * r_fma(Fn[k] - fhi[k], T.gR(n), r_fma(Fs[k] - flo[k], T.gL(n), dF[k][n]));
     if (actY) bad = bad || b1 || b2;
   }
+
+  double qrow[4][N1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
+  __syncthreads();  // every row has been read
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = (double)ry[k][n];
 
   // ---- D: row sweep ----
   R rx[4][N1];
@@ -248,9 +290,10 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int n = 0; n < N1; ++n)
-        rx[k][n] = rd * r_fma(Fe[k] - fhi[k], T.gR[n], r_fma(Fw[k] - flo[k], T.gL[n], dF[k][n]));
+        rx[k][n] = rd * r_fma(Fe[k] - fhi[k], T.gR(n), r_fma(Fw[k] - flo[k], T.gL(n), dF[k][n]));
     if (actX) bad = bad || b1 || b2;
   }
+
   __syncthreads();  // all column parts parked
 
 #pragma unroll
@@ -268,40 +311,39 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
     }
   __syncthreads();
 
-  // ---- E: coalesced epilogue (all q_n loads issued before the stores,
-  // which may overwrite q_n in place) ----
-  {
-    double vn[TC::NRUN][TC::NIT];
-    const bool need_qn = MODE == kStageRK && A.a != 0.0;
+  // ---- E: coalesced epilogue ----
+  // all of a wave's q_n loads are issued before its stores, which may
+  // overwrite q_n in place
+  const bool need_qn = MODE == kStageRK && A.a != 0.0;
+  double vn[TC::NRUN][TC::NIT];
 #pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = need_qn && sg < 4 * kTile && cy < nay;
-      const double* src = A.q_n + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+  for (int u = 0; u < TC::NRUN; ++u) {
+    const int sg = TC::run(wv, u);
+    const int k = sg >> 3, cy = sg & 7;
+    const bool ok = need_qn && sg < 4 * kTile && cy < nay;
+    const double* src = A.q_n + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
 #pragma unroll
-      for (int it = 0; it < TC::NIT; ++it) {
-        const int f = it * 64 + lane;
-        vn[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
-      }
+    for (int it = 0; it < TC::NIT; ++it) {
+      const int f = it * 64 + lane;
+      vn[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
     }
+  }
 #pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = sg < 4 * kTile && cy < nay;
-      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
-      const double* img = qs + k * VS + cy * kTile * S;
+  for (int u = 0; u < TC::NRUN; ++u) {
+    const int sg = TC::run(wv, u);
+    const int k = sg >> 3, cy = sg & 7;
+    const bool ok = sg < 4 * kTile && cy < nay;
+    const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+    const double* img = qs + k * VS + cy * kTile * S;
 #pragma unroll
-      for (int it = 0; it < TC::NIT; ++it) {
-        const int f = it * 64 + lane;
-        if (ok && f < seg_len) {
-          const double v = img[tc.loff[it]];
-          if (MODE == kStageRK)
-            A.q_dst[gb + f] = need_qn ? fma(A.a, vn[u][it], v) : v;
-          else
-            static_cast<R*>(A.r_out)[gb + f] = (R)v;
-        }
+    for (int it = 0; it < TC::NIT; ++it) {
+      const int f = it * 64 + lane;
+      if (ok && f < seg_len) {
+        const double v = img[tc.loff[it]];
+        if (MODE == kStageRK)
+          A.q_dst[gb + f] = need_qn ? fma(A.a, vn[u][it], v) : v;
+        else
+          static_cast<R*>(A.r_out)[gb + f] = (R)v;
       }
     }
   }
@@ -312,8 +354,9 @@ __global__ __launch_bounds__(64 * (P + 1)) void stage_kernel(Geometry G, KTab<R,
 template <int P, typename R>
 static hipError_t launch_stage_t(int mode, const Geometry& g, const Tables1D& T,
                                  const StageArgs& a, hipStream_t s) {
+  constexpr int TPW = TilesPerGroup<P + 1, R>::value;
   const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T);
-  const dim3 grid(g.ntx * g.nty), block(64 * (P + 1));
+  const dim3 grid((g.ntx * g.nty + TPW - 1) / TPW), block(64 * (P + 1) * TPW);
   if (mode == kStageRK)
     hipLaunchKernelGGL((stage_kernel<P, R, kStageRK>), grid, block, 0, s, g, kt, a);
   else

@@ -88,10 +88,21 @@ bool build_tables(int P, Tables1D* T) {
         T->ep[l] = v;
     }
   }
+  // the nodes are symmetric, so D[n-1-i][n-1-l] = -D[i][l],
+  // l_l(+1) = l_{n-1-l}(-1) and gR'(xi_i) = -gL'(xi_{n-1-i}); rounding in the
+  // formulas above can break these by an ulp, so the upper half is set from
+  // the lower half (the kernels rely on the identities holding exactly)
   for (int i = 0; i < n; ++i) {
-    T->gLp[i] = -T->em[i] / T->w[i];
-    T->gRp[i] = T->ep[i] / T->w[i];
+    const int mi = n - 1 - i;
+    for (int l = 0; l < n; ++l) {
+      const int ml = n - 1 - l;
+      if (i > mi) T->D[i][l] = -T->D[mi][ml];
+      else if (i == mi) T->D[i][l] = l < ml ? T->D[i][l] : l > ml ? -T->D[i][ml] : 0.0;
+    }
+    T->ep[i] = T->em[mi];
   }
+  for (int i = 0; i < n; ++i) T->gLp[i] = -T->em[i] / T->w[i];
+  for (int i = 0; i < n; ++i) T->gRp[i] = -T->gLp[n - 1 - i];
   return true;
 }
 

@@ -102,10 +102,10 @@ __device__ __forceinline__ void line_adj_prep(const double q[4][N1], const doubl
   for (int k = 0; k < 4; ++k) {
 #pragma unroll
     for (int n = 0; n < N1; ++n) L.a[k][n] = rd * v[k][n];
-    L.qlo[k] = dot_n<N1>(T.em, q[k]);
-    L.qhi[k] = dot_n<N1>(T.ep, q[k]);
-    L.slo[k] = dot_n<N1>(T.gL, L.a[k]);
-    L.shi[k] = dot_n<N1>(T.gR, L.a[k]);
+    L.qlo[k] = dot_n<N1>([&](int n) { return T.em(n); }, q[k]);
+    L.qhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, q[k]);
+    L.slo[k] = dot_n<N1>([&](int n) { return T.gL(n); }, L.a[k]);
+    L.shi[k] = dot_n<N1>([&](int n) { return T.gR(n); }, L.a[k]);
   }
 }
 
@@ -122,14 +122,14 @@ __device__ __forceinline__ void line_adj_finish(const double q[4][N1], const Lin
     for (int k = 0; k < 4; ++k) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < N1; ++i) s += T.D[i][l] * L.a[k][i];
-      cf[k] = s - L.slo[k] * T.em[l] - L.shi[k] * T.ep[l];
+      for (int i = 0; i < N1; ++i) s += T.D(i, l) * L.a[k][i];
+      cf[k] = s - L.slo[k] * T.em(l) - L.shi[k] * T.ep(l);
     }
     const double qp[4] = {q[0][l], q[1][l], q[2][l], q[3][l]};
     double jt[4];
     flux_jac_t<AX>(qp, gam, cf, jt);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[k][l] = jt[k] + T.em[l] * clo[k] + T.ep[l] * chi[k];
+    for (int k = 0; k < 4; ++k) out[k][l] = jt[k] + T.em(l) * clo[k] + T.ep(l) * chi[k];
   }
 }
 
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wv = tid >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int tile = xcd_tile(blockIdx.x, G.ntx * G.nty);
   const int tx = tile % G.ntx, ty = tile / G.ntx;
   const int I0 = tx * kTile, J0 = ty * kTile;
@@ -234,8 +234,8 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
       const bool hi_face = (hs == 0 || hs == 2);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        oq[k] = dot_n<N1>(hi_face ? T.ep : T.em, lq[k]);
-        os[k] = dot_n<N1>(hi_face ? T.gR : T.gL, la[k]);
+        oq[k] = dot_n<N1>([&](int n) { return hi_face ? T.ep(n) : T.em(n); }, lq[k]);
+        os[k] = dot_n<N1>([&](int n) { return hi_face ? T.gR(n) : T.gL(n); }, la[k]);
       }
     }
   }
@@ -265,8 +265,8 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
     double iq[4], is[4], s[4], qL[4], qR[4], cL[4], cR[4], cin[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      iq[k] = dot_n<N1>(lo_side ? T.em : T.ep, lq[k]);
-      is[k] = dot_n<N1>(lo_side ? T.gL : T.gR, la[k]);
+      iq[k] = dot_n<N1>([&](int n) { return lo_side ? T.em(n) : T.ep(n); }, lq[k]);
+      is[k] = dot_n<N1>([&](int n) { return lo_side ? T.gL(n) : T.gR(n); }, la[k]);
       if (!hout) oq[k] = iq[k];
       s[k] = hout ? is[k] + os[k] : is[k];
       qL[k] = lo_side ? oq[k] : iq[k];
@@ -288,19 +288,20 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   const int cxY = lane >> 3, cyY = lane & 7, eY = cyY * kTile + cxY;
   const bool actX = cxX < nax && cyX < nay;
   const bool actY = cxY < nax && cyY < nay;
-  double qrow[4][N1], vrow[4][N1], qcol[4][N1], vcol[4][N1];
+  // Each sweep holds only its own line: the column sweep's result stays in
+  // registers until every lane has read its row, then replaces q in LDS.
+  double qcol[4][N1], vcol[4][N1];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
-      qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
-      vrow[k][n] = vs[k * VS + eX * S + wv * N1 + n];
       qcol[k][n] = qs[k * VS + eY * S + n * N1 + wv];
       vcol[k][n] = vs[k * VS + eY * S + n * N1 + wv];
     }
-  __syncthreads();
+  __syncthreads();  // tile-boundary cotangents are in hC
 
   // ---- column sweep (y) ----
+  double oc[4][N1];
   {
     LineAdj<N1, 1> L;
     line_adj_prep<N1, 1>(qcol, vcol, T, rdy, L);
@@ -327,14 +328,23 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
 #pragma unroll
       for (int k = 0; k < 4; ++k) chi[k] = hC[3][cxY][wv][k];
     }
-    double oc[4][N1];
     line_adj_finish<N1, 1>(qcol, L, clo, chi, T, gam, oc);
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = oc[k][n];
     if (actY) bad = bad || b2;
   }
+
+  double qrow[4][N1], vrow[4][N1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
+      vrow[k][n] = vs[k * VS + eX * S + wv * N1 + n];
+    }
+  __syncthreads();  // every row has been read
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = oc[k][n];
 
   // ---- row sweep (x) ----
   double orow[4][N1];
