@@ -25,7 +25,7 @@
 //  B  those lanes finish the Rusanov flux on the tile-boundary faces; every
 //     lane reads its column out of LDS;
 //  C  column sweep: interior face states travel between lanes by wave
-//     shuffles (neighbours along a column are adjacent lanes). The column
+//     shuffles (neighbours along a column are 8 lanes apart). The column
 //     residual stays in registers until every lane has read its row, then
 //     replaces the tile image in LDS;
 //  D  row sweep the same way; this tile's q_n loads are issued, then the two
@@ -203,10 +203,13 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
     for (int k = 0; k < 4; ++k) hF[hs][hp][hm][k] = Fh[k];
   }
 
-  // x sweep: lane -> element (cx = lane % 8, cy = lane / 8), row wv
-  // y sweep: lane -> element (cx = lane / 8, cy = lane % 8), column wv
+  // both sweeps: lane -> element (cx = lane % 8, cy = lane / 8); row wv in
+  // the x sweep (x neighbours 1 lane apart), column wv in the y sweep (y
+  // neighbours 8 lanes apart). In both sweeps consecutive lanes read
+  // consecutive elements of the odd-stride image, which spreads a wave's
+  // LDS accesses over the banks.
   const int cxX = lane & 7, cyX = lane >> 3, eX = lane;
-  const int cxY = lane >> 3, cyY = lane & 7, eY = cyY * kTile + cxY;
+  const int cxY = lane & 7, cyY = lane >> 3, eY = lane;
   const bool actX = cxX < nax && cyX < nay;
   const bool actY = cxY < nax && cyY < nay;
   R qcol[4][N1];
@@ -226,7 +229,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
     line_ops<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     R qnb[4], Fs[4], Fn[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], 1, 64);
+    for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], kTile, 64);
     rusanov<1>(qnb, qlo, gam, gm1, Fs, b2);
     if (cyY == 0) {
 #pragma unroll
@@ -234,7 +237,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       b2 = false;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) Fn[k] = __shfl_down(Fs[k], 1, 64);
+    for (int k = 0; k < 4; ++k) Fn[k] = __shfl_down(Fs[k], kTile, 64);
     if (cyY == nay - 1) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) Fn[k] = hF[3][cxY][wv][k];

@@ -284,8 +284,10 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
     }
   }
 
+  // one lane -> element map for both sweeps: x neighbours are 1 lane
+  // apart, y neighbours 8 lanes apart
   const int cxX = lane & 7, cyX = lane >> 3, eX = lane;
-  const int cxY = lane >> 3, cyY = lane & 7, eY = cyY * kTile + cxY;
+  const int cxY = lane & 7, cyY = lane >> 3, eY = lane;
   const bool actX = cxX < nax && cyX < nay;
   const bool actY = cxY < nax && cyY < nay;
   // Each sweep holds only its own line: the column sweep's result stays in
@@ -308,8 +310,8 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
     double qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      qnb[k] = __shfl_up(L.qhi[k], 1, 64);
-      snb[k] = __shfl_up(L.shi[k], 1, 64);
+      qnb[k] = __shfl_up(L.qhi[k], kTile, 64);
+      snb[k] = __shfl_up(L.shi[k], kTile, 64);
       s[k] = L.slo[k] + snb[k];
     }
     bool b2 = false;
@@ -317,7 +319,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       clo[k] = cR[k];
-      chi[k] = __shfl_down(cL[k], 1, 64);
+      chi[k] = __shfl_down(cL[k], kTile, 64);
     }
     if (cyY == 0) {
 #pragma unroll
