@@ -29,6 +29,8 @@ struct KTab {
   R Dh[H][N1];
   R em_[N1];
   R gL_[N1];
+  R gam, gm1;  // gamma and gamma - 1
+  R rdx, rdy;  // -2/dx and -2/dy: the reference-to-physical derivative factors
   __device__ __forceinline__ R D(int i, int l) const {
     if (i < N1 - 1 - i) return Dh[i][l];
     if (i > N1 - 1 - i) return -Dh[N1 - 1 - i][N1 - 1 - l];
@@ -44,8 +46,12 @@ struct KTab {
 };
 
 template <typename R, int N1>
-inline KTab<R, N1> make_ktab(const Tables1D& T) {
+inline KTab<R, N1> make_ktab(const Tables1D& T, const Geometry& G) {
   KTab<R, N1> k;
+  k.gam = (R)G.gamma;
+  k.gm1 = (R)(G.gamma - 1.0);
+  k.rdx = (R)(-2.0 / G.dx);
+  k.rdy = (R)(-2.0 / G.dy);
   for (int i = 0; i < KTab<R, N1>::H; ++i)
     for (int l = 0; l < N1; ++l) k.Dh[i][l] = (R)T.D[i][l];
   for (int i = 0; i < N1; ++i) {

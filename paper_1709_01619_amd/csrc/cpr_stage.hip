@@ -72,7 +72,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   const int nax = live ? min(kTile, G.nx - I0) : 0;
   const int nay = live ? min(kTile, G.ny - J0) : 0;
   const size_t plane = (size_t)G.ny * G.nx * NSP;
-  const R gam = (R)G.gamma, gm1 = (R)(G.gamma - 1.0);
+  const R gam = T.gam, gm1 = T.gm1;
   double* qs = qs_all[slot];
   auto hF = hF_all[slot];
   bool bad = false;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
 #pragma unroll
       for (int it = 0; it < TC::NIT; ++it) {
         const int f = it * 64 + lane;
-        v[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
+        if (ok && f < seg_len) v[u][it] = src[f];
       }
     }
     double hraw[4][N1];
@@ -242,7 +242,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
 #pragma unroll
       for (int k = 0; k < 4; ++k) Fn[k] = hF[3][cxY][wv][k];
     }
-    const R rd = (R)(-2.0 / G.dy);
+    const R rd = T.rdy;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -288,7 +288,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
 #pragma unroll
       for (int k = 0; k < 4; ++k) Fe[k] = hF[1][cyX][wv][k];
     }
-    const R rd = (R)(-2.0 / G.dx);
+    const R rd = T.rdx;
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -328,25 +328,45 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
 #pragma unroll
     for (int it = 0; it < TC::NIT; ++it) {
       const int f = it * 64 + lane;
-      vn[u][it] = (ok && f < seg_len) ? src[f] : 0.0;
+      if (ok && f < seg_len) vn[u][it] = src[f];
     }
   }
+  // every output value of the wave is formed before the first store: a
+  // store issued between two uses of loaded data would make the later use
+  // wait for the store as well
 #pragma unroll
   for (int u = 0; u < TC::NRUN; ++u) {
     const int sg = TC::run(wv, u);
-    const int k = sg >> 3, cy = sg & 7;
+    const int cy = sg & 7, k = sg >> 3;
     const bool ok = sg < 4 * kTile && cy < nay;
-    const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
     const double* img = qs + k * VS + cy * kTile * S;
 #pragma unroll
     for (int it = 0; it < TC::NIT; ++it) {
       const int f = it * 64 + lane;
       if (ok && f < seg_len) {
         const double v = img[tc.loff[it]];
+        vn[u][it] = need_qn ? fma(A.a, vn[u][it], v) : v;
+      }
+    }
+  }
+  // the loads above sit in lane-predicated blocks, after which the
+  // compiler cannot tell that they have all returned and would wait for
+  // every earlier store before each store; one explicit wait settles it
+  __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+  for (int u = 0; u < TC::NRUN; ++u) {
+    const int sg = TC::run(wv, u);
+    const int k = sg >> 3, cy = sg & 7;
+    const bool ok = sg < 4 * kTile && cy < nay;
+    const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+    for (int it = 0; it < TC::NIT; ++it) {
+      const int f = it * 64 + lane;
+      if (ok && f < seg_len) {
         if (MODE == kStageRK)
-          A.q_dst[gb + f] = need_qn ? fma(A.a, vn[u][it], v) : v;
+          A.q_dst[gb + f] = vn[u][it];
         else
-          static_cast<R*>(A.r_out)[gb + f] = (R)v;
+          static_cast<R*>(A.r_out)[gb + f] = (R)vn[u][it];
       }
     }
   }
@@ -358,7 +378,7 @@ template <int P, typename R>
 static hipError_t launch_stage_t(int mode, const Geometry& g, const Tables1D& T,
                                  const StageArgs& a, hipStream_t s) {
   constexpr int TPW = TilesPerGroup<P + 1, R>::value;
-  const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T);
+  const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T, g);
   const dim3 grid((g.ntx * g.nty + TPW - 1) / TPW), block(64 * (P + 1) * TPW);
   if (mode == kStageRK)
     hipLaunchKernelGGL((stage_kernel<P, R, kStageRK>), grid, block, 0, s, g, kt, a);

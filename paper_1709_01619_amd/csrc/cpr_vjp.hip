@@ -152,8 +152,8 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   const int I0 = tx * kTile, J0 = ty * kTile;
   const int nax = min(kTile, G.nx - I0), nay = min(kTile, G.ny - J0);
   const size_t plane = (size_t)G.ny * G.nx * NSP;
-  const double gam = G.gamma;
-  const double rdx = -2.0 / G.dx, rdy = -2.0 / G.dy;
+  const double gam = T.gam;
+  const double rdx = T.rdx, rdy = T.rdy;
   bool bad = false;
 
   // tile of q and of v -> LDS; each wave issues all its loads of an array
@@ -409,12 +409,13 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
         yv[u][it] = (in && A.y != nullptr) ? A.y[gb + f] : 0.0;
       }
     }
+    // every output value is formed before the first store (see the stage
+    // kernel's epilogue), then one explicit wait, then the stores
 #pragma unroll
     for (int u = 0; u < TC::NRUN; ++u) {
       const int sg = TC::run(wv, u);
       const int k = sg >> 3, cy = sg & 7;
       const bool ok = sg < 4 * kTile && cy < nay;
-      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
       const double* img = qs + k * VS + cy * kTile * S;
 #pragma unroll
       for (int it = 0; it < TC::NIT; ++it) {
@@ -423,8 +424,21 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
           double o = img[tc.loff[it]];
           if (A.x != nullptr) o += A.beta * xv[u][it];
           if (A.y != nullptr) o += A.gam * yv[u][it];
-          A.out[gb + f] = o;
+          xv[u][it] = o;
         }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) A.out[gb + f] = xv[u][it];
       }
     }
   }
@@ -434,7 +448,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
 template <int P>
 static hipError_t launch_vjp_t(const Geometry& g, const Tables1D& T, const VjpArgs& a,
                                hipStream_t s) {
-  const KTab<double, P + 1> kt = make_ktab<double, P + 1>(T);
+  const KTab<double, P + 1> kt = make_ktab<double, P + 1>(T, g);
   hipLaunchKernelGGL((vjp_kernel<P>), dim3(g.ntx * g.nty), dim3(64 * (P + 1)), 0, s, g, kt, a);
   return hipGetLastError();
 }
