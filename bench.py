@@ -251,32 +251,40 @@ def main(argv=None):
     adj = None
     if not a.quick:
         import inputs
-        s = Solver(3, 128, 128)
-        x, y = s.coords()
-        V = inputs.Vortex()
-        q0n = V.conserved(x.cpu().numpy(), y.cpu().numpy())
-        q0n[0] += inputs.gaussian_perturbation(q0n[0].shape, 1e-3, 0)
-        rho_ex = torch.from_numpy(V.conserved(x.cpu().numpy(), y.cpu().numpy(), 0.4)[0]).cuda()
-        W = s.quad_weights()
-        q0 = torch.from_numpy(q0n).cuda().requires_grad_(True)
-        for rep in range(2):   # first pass warms up
-            if q0.grad is not None:
-                q0.grad = None
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            qT = Rollout.apply(q0, s, 1e-3, 400, 50)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            J = 0.5 * ((qT[0] - rho_ex) ** 2 * W).sum()
-            J.backward()
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-        adj = {"workload": "P=3 128x128 perturbed vortex, 400 steps dt=1e-3, checkpoint 50",
-               "forward_s_per_step": (t1 - t0) / 400, "backward_s_per_step": (t2 - t1) / 400,
-               "adjoint_s_per_step": (t2 - t0) / 400, "misfit": float(J.item())}
-        log("adjoint", adj)
-        del s
-
+        adj = {"workload": "P=3 128x128 perturbed vortex, 400 steps dt=1e-3, checkpoint 50"}
+        grads = {}
+        for prec in ("fp64", "fp32_bulk"):
+            s = Solver(3, 128, 128, precision=prec)
+            x, y = s.coords()
+            V = inputs.Vortex()
+            q0n = V.conserved(x.cpu().numpy(), y.cpu().numpy())
+            q0n[0] += inputs.gaussian_perturbation(q0n[0].shape, 1e-3, 0)
+            rho_ex = torch.from_numpy(V.conserved(x.cpu().numpy(), y.cpu().numpy(), 0.4)[0]).cuda()
+            W = s.quad_weights()
+            q0 = torch.from_numpy(q0n).cuda().requires_grad_(True)
+            for rep in range(2):   # first pass warms up
+                if q0.grad is not None:
+                    q0.grad = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                qT = Rollout.apply(q0, s, 1e-3, 400, 50)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                J = 0.5 * ((qT[0] - rho_ex) ** 2 * W).sum()
+                J.backward()
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+            grads[prec] = q0.grad.detach().clone()
+            r = {"forward_s_per_step": (t1 - t0) / 400, "backward_s_per_step": (t2 - t1) / 400,
+                 "adjoint_s_per_step": (t2 - t0) / 400, "misfit": float(J.item())}
+            if prec == "fp64":
+                adj.update(r)
+            else:
+                r["gradient_rel_err_vs_fp64"] = float(
+                    (grads["fp32_bulk"] - grads["fp64"]).abs().max() / grads["fp64"].abs().max())
+                adj["fp32_bulk"] = r
+            log("adjoint", prec, r)
+            del s
     # ---- scale: P=4 1024^2 (104.9M unknowns), FP64 and FP32-bulk ----
     scale = None
     if not a.quick:

@@ -124,20 +124,23 @@ cpr_status cpr_rk3_step(cpr_ctx* ctx, double* q, double dt, int32_t apply_limite
 cpr_status cpr_limit(cpr_ctx* ctx, double* q, int32_t* flags, int32_t* n_troubled);
 
 /* out = (dR/dq)^T v at state q: the exact transpose of cpr_residual's
- * float64 map, including the derivative of Rusanov's wave-speed bound
+ * map, including the derivative of Rusanov's wave-speed bound
  * lam = max(|u_n|+c) over the two face states (derivative of |u_n| at 0 is
  * +1; where the two speeds tie to 1e-12 relative, the mean of the two
- * sides' gradients is used). q, v,
- * out: device float64 states; out must not alias q or v. CPR_FP64 contexts
- * only (CPR_EUNSUPPORTED otherwise). */
+ * sides' gradients is used). In CPR_FP32_BULK contexts the transpose is
+ * evaluated in float32 (as the residual is) and its two sweep parts are
+ * summed in float64. q, v, out: device float64 states; out must not alias
+ * q or v. */
 cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, double* out);
 
 /* Discrete adjoint of one unlimited SSP-RK3 step of size dt > 0 from q_n:
  * lam_n = (d q(n+1) / d q_n)^T lam_np1, recomputing the stage states.
  *   lam2 = 2/3 (lam3 + dt J(q2)^T lam3); lam1 = 1/4 (lam2 + dt J(q1)^T lam2);
  *   lam_n = lam1 + dt J(qn)^T lam1 + 1/3 lam3 + 3/4 lam2.
- * All pointers device float64 states; lam_n may alias lam_np1.
- * CPR_EUNSUPPORTED on a context with a limiter or in CPR_FP32_BULK mode. */
+ * All pointers device float64 states; lam_n may alias lam_np1. In
+ * CPR_FP32_BULK contexts the stage states are recomputed with the float32
+ * residual and the J^T products are float32 (cpr_residual_vjp); the lam
+ * combinations are float64. CPR_EUNSUPPORTED on a context with a limiter. */
 cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt,
                             const double* lam_np1, double* lam_n);
 

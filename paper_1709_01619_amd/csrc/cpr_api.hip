@@ -121,7 +121,7 @@ cpr_status vjp(cpr_ctx* c, const double* q, const double* v, const double* x, co
   a.beta = beta;
   a.gam = gam;
   a.err = c->iscr;
-  HIP_TRY(c, launch_vjp(c->cfg.order_p, c->geo, c->tab, a, c->stream), "adjoint kernel launch");
+  HIP_TRY(c, launch_vjp(c->cfg.order_p, c->cfg.precision == CPR_FP32_BULK, c->geo, c->tab, a, c->stream), "adjoint kernel launch");
   return CPR_OK;
 }
 
@@ -299,10 +299,6 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
     set_err(ctx, "cpr_residual_vjp: out must not alias q or v");
     return CPR_EINVAL;
   }
-  if (ctx->cfg.precision != CPR_FP64) {
-    set_err(ctx, "cpr_residual_vjp: float64 contexts only");
-    return CPR_EUNSUPPORTED;
-  }
   return vjp(ctx, q, v, nullptr, nullptr, out, 0.0, 1.0, 0.0, 0.0);
 }
 
@@ -312,10 +308,6 @@ cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt, const do
   if (!(std::isfinite(dt) && dt > 0.0)) return CPR_EINVAL;
   if (ctx->cfg.limiter != CPR_LIM_NONE) {
     set_err(ctx, "cpr_adjoint_step: the limiter is not differentiated");
-    return CPR_EUNSUPPORTED;
-  }
-  if (ctx->cfg.precision != CPR_FP64) {
-    set_err(ctx, "cpr_adjoint_step: float64 contexts only");
     return CPR_EUNSUPPORTED;
   }
   if ((const double*)lam_n == q_n) return CPR_EINVAL;

@@ -63,7 +63,7 @@ struct VjpArgs {
   double alpha, delta, beta, gam;
   int* err;
 };
-hipError_t launch_vjp(int P, const Geometry& g, const Tables1D& T, const VjpArgs& a,
+hipError_t launch_vjp(int P, bool fp32, const Geometry& g, const Tables1D& T, const VjpArgs& a,
                       hipStream_t s);
 
 // Limiter: element means then detect + limit in place.

@@ -1,5 +1,7 @@
 // Discrete adjoint of the CPR residual: out = alpha v + delta J(q)^T v +
-// beta x + gam y, J = dR/dq of the float64 residual of cpr_stage.hip.
+// beta x + gam y, J = dR/dq of the residual of cpr_stage.hip. The line
+// algebra runs in the residual's compute type R (float64, or float32 for the
+// FP32-bulk residual); q, v, x, y, out and the combination are float64.
 //
 // Same tile and lane layout as the forward stage kernel: an 8x8 element
 // tile per workgroup, wave w on line w of every element. Each line is the
@@ -22,33 +24,31 @@
 namespace cpr {
 
 // (dF_AX/dq)^T s at state q.
-template <int AX>
-__device__ __forceinline__ void flux_jac_t(const double q[4], double gam, const double s[4],
-                                           double out[4]) {
+template <int AX, typename R>
+__device__ __forceinline__ void flux_jac_t(const R q[4], R gam, const R s[4], R out[4]) {
   constexpr int n = 1 + AX, t = 2 - AX;
-  const double ir = 1.0 / q[0];
-  const double un = q[n] * ir, ut = q[t] * ir;
-  const double gm1 = gam - 1.0;
-  const double ke = 0.5 * (un * un + ut * ut);
-  const double p = gm1 * (q[3] - q[0] * ke);
-  const double H = (q[3] + p) * ir;
-  const double phi = gm1 * ke;
+  const R ir = R(1) / q[0];
+  const R un = q[n] * ir, ut = q[t] * ir;
+  const R gm1 = gam - R(1);
+  const R ke = R(0.5) * (un * un + ut * ut);
+  const R p = gm1 * (q[3] - q[0] * ke);
+  const R H = (q[3] + p) * ir;
+  const R phi = gm1 * ke;
   out[0] = (phi - un * un) * s[n] - un * ut * s[t] + un * (phi - H) * s[3];
-  out[n] = s[0] + (3.0 - gam) * un * s[n] + ut * s[t] + (H - gm1 * un * un) * s[3];
+  out[n] = s[0] + (R(3) - gam) * un * s[n] + ut * s[t] + (H - gm1 * un * un) * s[3];
   out[t] = -gm1 * ut * s[n] + un * s[t] - gm1 * un * ut * s[3];
   out[3] = gm1 * s[n] + gam * un * s[3];
 }
 
 // Gradient of |u_n| + c with respect to q.
-template <int AX>
-__device__ __forceinline__ void wave_speed_grad(const double q[4], double gam, double c,
-                                                double g[4]) {
+template <int AX, typename R>
+__device__ __forceinline__ void wave_speed_grad(const R q[4], R gam, R c, R g[4]) {
   constexpr int n = 1 + AX, t = 2 - AX;
-  const double ir = 1.0 / q[0];
-  const double un = q[n] * ir, ut = q[t] * ir;
-  const double gg = gam * (gam - 1.0);
-  const double sgn = un >= 0.0 ? 1.0 : -1.0;
-  const double i2c = 0.5 / c;
+  const R ir = R(1) / q[0];
+  const R un = q[n] * ir, ut = q[t] * ir;
+  const R gg = gam * (gam - R(1));
+  const R sgn = un >= R(0) ? R(1) : R(-1);
+  const R i2c = R(0.5) / c;
   g[0] = gg * (-q[3] * ir * ir + (un * un + ut * ut) * ir) * i2c - sgn * un * ir;
   g[n] = -gg * un * ir * i2c + sgn * ir;
   g[t] = -gg * ut * ir * i2c;
@@ -56,48 +56,47 @@ __device__ __forceinline__ void wave_speed_grad(const double q[4], double gam, d
 }
 
 // Cotangents of both face states of the Rusanov flux for output cotangent s.
-template <int AX>
-__device__ __forceinline__ void rusanov_vjp(const double qL[4], const double qR[4],
-                                            const double s[4], double gam, double cL[4],
-                                            double cR[4], bool& bad) {
+template <int AX, typename R>
+__device__ __forceinline__ void rusanov_vjp(const R qL[4], const R qR[4], const R s[4], R gam,
+                                            R cL[4], R cR[4], bool& bad) {
   constexpr int n = 1 + AX;
-  const double gm1 = gam - 1.0;
-  const double irL = 1.0 / qL[0], irR = 1.0 / qR[0];
-  const double pL = gm1 * (qL[3] - 0.5 * (qL[1] * qL[1] + qL[2] * qL[2]) * irL);
-  const double pR = gm1 * (qR[3] - 0.5 * (qR[1] * qR[1] + qR[2] * qR[2]) * irR);
-  const double cLs = sqrt(gam * pL * irL), cRs = sqrt(gam * pR * irR);
-  const double lL = fabs(qL[n] * irL) + cLs, lR = fabs(qR[n] * irR) + cRs;
-  const double lam = lL >= lR ? lL : lR;
-  const bool tie = fabs(lL - lR) <= 1e-12 * lam;
-  const double wl = tie ? 0.5 : (lL > lR ? 1.0 : 0.0);
-  const double wr = 1.0 - wl;
-  double jump = 0.0;
+  const R gm1 = gam - R(1);
+  const R irL = R(1) / qL[0], irR = R(1) / qR[0];
+  const R pL = gm1 * (qL[3] - R(0.5) * (qL[1] * qL[1] + qL[2] * qL[2]) * irL);
+  const R pR = gm1 * (qR[3] - R(0.5) * (qR[1] * qR[1] + qR[2] * qR[2]) * irR);
+  const R cLs = sqrt(gam * pL * irL), cRs = sqrt(gam * pR * irR);
+  const R lL = fabs(qL[n] * irL) + cLs, lR = fabs(qR[n] * irR) + cRs;
+  const R lam = lL >= lR ? lL : lR;
+  const bool tie = fabs(lL - lR) <= R(1e-12) * lam;
+  const R wl = tie ? R(0.5) : (lL > lR ? R(1) : R(0));
+  const R wr = R(1) - wl;
+  R jump = R(0);
 #pragma unroll
   for (int k = 0; k < 4; ++k) jump += s[k] * (qR[k] - qL[k]);
-  double aL[4], aR[4], gL[4], gR[4];
+  R aL[4], aR[4], gL[4], gR[4];
   flux_jac_t<AX>(qL, gam, s, aL);
   flux_jac_t<AX>(qR, gam, s, aR);
   wave_speed_grad<AX>(qL, gam, cLs, gL);
   wave_speed_grad<AX>(qR, gam, cRs, gR);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    cL[k] = 0.5 * aL[k] + 0.5 * lam * s[k] - 0.5 * jump * wl * gL[k];
-    cR[k] = 0.5 * aR[k] - 0.5 * lam * s[k] - 0.5 * jump * wr * gR[k];
+    cL[k] = R(0.5) * aL[k] + R(0.5) * lam * s[k] - R(0.5) * jump * wl * gL[k];
+    cR[k] = R(0.5) * aR[k] - R(0.5) * lam * s[k] - R(0.5) * jump * wr * gR[k];
   }
   bad = bad || nonphysical(qL[0], pL) || nonphysical(qR[0], pR);
 }
 
-template <int N1, int AX>
+template <int N1, int AX, typename R>
 struct LineAdj {
-  double qlo[4], qhi[4];  // face states
-  double slo[4], shi[4];  // own face flux cotangents (sigma)
-  double a[4][N1];        // -(2/h) v on the line
+  R qlo[4], qhi[4];  // face states
+  R slo[4], shi[4];  // own face flux cotangents (sigma)
+  R a[4][N1];        // -(2/h) v on the line
 };
 
-template <int N1, int AX>
-__device__ __forceinline__ void line_adj_prep(const double q[4][N1], const double v[4][N1],
-                                              const KTab<double, N1>& T, double rd,
-                                              LineAdj<N1, AX>& L) {
+template <int N1, int AX, typename R>
+__device__ __forceinline__ void line_adj_prep(const R q[4][N1], const R v[4][N1],
+                                              const KTab<R, N1>& T, R rd,
+                                              LineAdj<N1, AX, R>& L) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
 #pragma unroll
@@ -110,39 +109,37 @@ __device__ __forceinline__ void line_adj_prep(const double q[4][N1], const doubl
 }
 
 // cot q on the line from the face-state cotangents clo, chi.
-template <int N1, int AX>
-__device__ __forceinline__ void line_adj_finish(const double q[4][N1], const LineAdj<N1, AX>& L,
-                                                const double clo[4], const double chi[4],
-                                                const KTab<double, N1>& T, double gam,
-                                                double out[4][N1]) {
+template <int N1, int AX, typename R>
+__device__ __forceinline__ void line_adj_finish(const R q[4][N1], const LineAdj<N1, AX, R>& L,
+                                                const R clo[4], const R chi[4],
+                                                const KTab<R, N1>& T, R gam, R out[4][N1]) {
 #pragma unroll
   for (int l = 0; l < N1; ++l) {
-    double cf[4];
+    R cf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      double s = 0.0;
+      R s = R(0);
 #pragma unroll
       for (int i = 0; i < N1; ++i) s += T.D(i, l) * L.a[k][i];
       cf[k] = s - L.slo[k] * T.em(l) - L.shi[k] * T.ep(l);
     }
-    const double qp[4] = {q[0][l], q[1][l], q[2][l], q[3][l]};
-    double jt[4];
+    const R qp[4] = {q[0][l], q[1][l], q[2][l], q[3][l]};
+    R jt[4];
     flux_jac_t<AX>(qp, gam, cf, jt);
 #pragma unroll
     for (int k = 0; k < 4; ++k) out[k][l] = jt[k] + T.em(l) * clo[k] + T.ep(l) * chi[k];
   }
 }
 
-template <int P>
-__global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<double, P + 1> T,
-                                                           VjpArgs A) {
+template <int P, typename R>
+__global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P + 1> T, VjpArgs A) {
   constexpr int N1 = P + 1;
   constexpr int NSP = N1 * N1;
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;
   constexpr int VS = 64 * S;
   __shared__ double qs[4 * VS];
   __shared__ double vs[4 * VS];
-  __shared__ double hC[4][kTile][N1][4];  // inside face-state cotangents at tile boundaries
+  __shared__ R hC[4][kTile][N1][4];  // inside face-state cotangents at tile boundaries
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -152,8 +149,8 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   const int I0 = tx * kTile, J0 = ty * kTile;
   const int nax = min(kTile, G.nx - I0), nay = min(kTile, G.ny - J0);
   const size_t plane = (size_t)G.ny * G.nx * NSP;
-  const double gam = T.gam;
-  const double rdx = T.rdx, rdy = T.rdy;
+  const R gam = T.gam;
+  const R rdx = T.rdx, rdy = T.rdy;
   bool bad = false;
 
   // tile of q and of v -> LDS; each wave issues all its loads of an array
@@ -195,7 +192,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   const bool halo = tid < 4 * kTile * N1;
   int hs = 0, hp = 0, hm = 0;
   bool hact = false, hout = false;
-  double oq[4] = {0, 0, 0, 0}, os[4] = {0, 0, 0, 0};
+  R oq[4] = {R(0), R(0), R(0), R(0)}, os[4] = {R(0), R(0), R(0), R(0)};
   if (halo) {
     hs = tid / (kTile * N1);
     const int r2 = tid - hs * (kTile * N1);
@@ -220,15 +217,15 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
     }
     if (hact && hout) {
       const size_t base = ((size_t)Jo * G.nx + Io) * NSP;
-      double lq[4][N1], la[4][N1];
-      const double rd = hs < 2 ? rdx : rdy;
+      R lq[4][N1], la[4][N1];
+      const R rd = hs < 2 ? rdx : rdy;
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int n = 0; n < N1; ++n) {
           const size_t g = k * plane + base + (hs < 2 ? hm * N1 + n : n * N1 + hm);
-          lq[k][n] = A.q[g];
-          la[k][n] = rd * A.v[g];
+          lq[k][n] = (R)A.q[g];
+          la[k][n] = rd * (R)A.v[g];
         }
       // the outside element's face that touches this tile
       const bool hi_face = (hs == 0 || hs == 2);
@@ -252,17 +249,17 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
       off = hm;
       stride = N1;
     }
-    const double rd = hs < 2 ? rdx : rdy;
-    double lq[4][N1], la[4][N1];
+    const R rd = hs < 2 ? rdx : rdy;
+    R lq[4][N1], la[4][N1];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int n = 0; n < N1; ++n) {
-        lq[k][n] = qs[k * VS + e * S + off + n * stride];
-        la[k][n] = rd * vs[k * VS + e * S + off + n * stride];
+        lq[k][n] = (R)qs[k * VS + e * S + off + n * stride];
+        la[k][n] = rd * (R)vs[k * VS + e * S + off + n * stride];
       }
     const bool lo_side = (hs == 0 || hs == 2);  // this tile's face is its low face
-    double iq[4], is[4], s[4], qL[4], qR[4], cL[4], cR[4], cin[4];
+    R iq[4], is[4], s[4], qL[4], qR[4], cL[4], cR[4], cin[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       iq[k] = dot_n<N1>([&](int n) { return lo_side ? T.em(n) : T.ep(n); }, lq[k]);
@@ -292,22 +289,22 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   const bool actY = cxY < nax && cyY < nay;
   // Each sweep holds only its own line: the column sweep's result stays in
   // registers until every lane has read its row, then replaces q in LDS.
-  double qcol[4][N1], vcol[4][N1];
+  R qcol[4][N1], vcol[4][N1];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
-      qcol[k][n] = qs[k * VS + eY * S + n * N1 + wv];
-      vcol[k][n] = vs[k * VS + eY * S + n * N1 + wv];
+      qcol[k][n] = (R)qs[k * VS + eY * S + n * N1 + wv];
+      vcol[k][n] = (R)vs[k * VS + eY * S + n * N1 + wv];
     }
   __syncthreads();  // tile-boundary cotangents are in hC
 
   // ---- column sweep (y) ----
-  double oc[4][N1];
+  R oc[4][N1];
   {
-    LineAdj<N1, 1> L;
+    LineAdj<N1, 1, R> L;
     line_adj_prep<N1, 1>(qcol, vcol, T, rdy, L);
-    double qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
+    R qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       qnb[k] = __shfl_up(L.qhi[k], kTile, 64);
@@ -334,26 +331,32 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
     if (actY) bad = bad || b2;
   }
 
-  double qrow[4][N1], vrow[4][N1];
+  R qrow[4][N1];
+  double vrow[4][N1];  // float64: the combination alpha v below uses it
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
-      qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
+      qrow[k][n] = (R)qs[k * VS + eX * S + wv * N1 + n];
       vrow[k][n] = vs[k * VS + eX * S + wv * N1 + n];
     }
   __syncthreads();  // every row has been read
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = oc[k][n];
+    for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = (double)oc[k][n];
 
   // ---- row sweep (x) ----
-  double orow[4][N1];
+  R orow[4][N1];
   {
-    LineAdj<N1, 0> L;
-    line_adj_prep<N1, 0>(qrow, vrow, T, rdx, L);
-    double qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
+    LineAdj<N1, 0, R> L;
+    R vr[4][N1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) vr[k][n] = (R)vrow[k][n];
+    line_adj_prep<N1, 0>(qrow, vr, T, rdx, L);
+    R qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       qnb[k] = __shfl_up(L.qhi[k], 1, 64);
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
       const int a = k * VS + eX * S + wv * N1 + n;
-      const double jt = orow[k][n] + qs[a];
+      const double jt = (double)orow[k][n] + qs[a];
       qs[a] = A.alpha * vrow[k][n] + A.delta * jt;
     }
   __syncthreads();
@@ -445,21 +448,21 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<doub
   if (bad) atomicOr(A.err, 1);
 }
 
-template <int P>
+template <int P, typename R>
 static hipError_t launch_vjp_t(const Geometry& g, const Tables1D& T, const VjpArgs& a,
                                hipStream_t s) {
-  const KTab<double, P + 1> kt = make_ktab<double, P + 1>(T, g);
-  hipLaunchKernelGGL((vjp_kernel<P>), dim3(g.ntx * g.nty), dim3(64 * (P + 1)), 0, s, g, kt, a);
+  const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T, g);
+  hipLaunchKernelGGL((vjp_kernel<P, R>), dim3(g.ntx * g.nty), dim3(64 * (P + 1)), 0, s, g, kt, a);
   return hipGetLastError();
 }
 
-hipError_t launch_vjp(int P, const Geometry& g, const Tables1D& T, const VjpArgs& a,
+hipError_t launch_vjp(int P, bool fp32, const Geometry& g, const Tables1D& T, const VjpArgs& a,
                       hipStream_t s) {
   switch (P) {
-    case 1: return launch_vjp_t<1>(g, T, a, s);
-    case 2: return launch_vjp_t<2>(g, T, a, s);
-    case 3: return launch_vjp_t<3>(g, T, a, s);
-    case 4: return launch_vjp_t<4>(g, T, a, s);
+    case 1: return fp32 ? launch_vjp_t<1, float>(g, T, a, s) : launch_vjp_t<1, double>(g, T, a, s);
+    case 2: return fp32 ? launch_vjp_t<2, float>(g, T, a, s) : launch_vjp_t<2, double>(g, T, a, s);
+    case 3: return fp32 ? launch_vjp_t<3, float>(g, T, a, s) : launch_vjp_t<3, double>(g, T, a, s);
+    case 4: return fp32 ? launch_vjp_t<4, float>(g, T, a, s) : launch_vjp_t<4, double>(g, T, a, s);
     default: return hipErrorInvalidValue;
   }
 }
