@@ -213,3 +213,46 @@ def test_fullsize_adjoint_gradient():
         worst = max(worst, abs(fd - ad) / abs(ad))
     print(f"adjoint FD worst relative error over 16 directions: {worst:.2e}")
     assert worst <= 1e-6
+
+
+def test_max_size_periodic_tiling():
+    """Largest size class: P=4 on 4700x4700 periodic elements, 2.2e9
+    unknowns (17.7 GB per state), so flat indices pass 2^31 and the last tile
+    column is ragged (4700 = 587 x 8 + 4). The state is a seeded random
+    47x47-element block repeated 100 x 100 times; the periodic scheme is
+    translation invariant, so the residual and one RK3 step of the large mesh
+    must equal the oracle's on the block, repeated, at every element, and the
+    conservation sums must be 10^4 times the block's."""
+    t = torch()
+    P, nb, rep = 4, 47, 100
+    h = 0.01
+    gb = cpr.Grid(P=P, nx=nb, ny=nb, x0=0.0, x1=nb * h, y0=0.0, y1=nb * h)
+    g = cpr.Grid(P=P, nx=nb * rep, ny=nb * rep, x0=0.0, x1=nb * rep * h, y0=0.0,
+                 y1=nb * rep * h)
+    qb = inputs.random_state((nb, nb, P + 1, P + 1), seed=4747)
+    say("max size: P=4 4700x4700 periodic tiling")
+    s = make_solver(g)
+    q = dev(qb).repeat(1, rep, rep, 1, 1)
+    assert q.numel() == 4 * 4700 * 4700 * 25 and q.is_contiguous()
+
+    def max_tiled_diff(big, small):
+        d = 0.0
+        sm = dev(small)
+        for k in range(4):
+            v = big[k].view(rep, nb, rep, nb, P + 1, P + 1)
+            d = max(d, float((v - sm[k][None, :, None]).abs().max().item()))
+        return d
+
+    Rb = cpr.residual(qb, gb)
+    R = s.residual(q)
+    scale = _fp32_scale(qb, gb)
+    assert max_tiled_diff(R, Rb) <= 16 * 2.0 ** -53 * scale
+    del R
+    Ib = cpr.integrals(qb, gb)
+    I = s.integrals(q)
+    assert np.max(np.abs(I - rep * rep * Ib) / np.abs(rep * rep * Ib)) <= 1e-12
+    dt = 2e-4
+    qb1 = cpr.rk3_step(qb, dt, gb)
+    s.step(q, dt)
+    assert max_tiled_diff(q, qb1) <= 1e-12 * np.max(np.abs(qb1))
+    del q, s
