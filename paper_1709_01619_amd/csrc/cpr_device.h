@@ -79,6 +79,23 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// sqrt(x) for positive, normal x: the hardware estimate y of 1/sqrt(x)
+// refined by the coupled Newton iteration for s = x y -> sqrt(x) and
+// h = y/2 -> 1/(2 sqrt(x)) (Markstein's method), then one correction with
+// the residual x - s^2. It skips the rescaling of tiny and huge arguments
+// that the library square root carries; the sound speeds here never need it
+// (a state with p <= 0 or rho <= 0 is flagged as non-physical).
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  const double d = fma(-s, s, x);
+  return fma(d, h, s);
+}
+__device__ __forceinline__ float sqrt_pos(float x) { return sqrtf(x); }
+
 // a*b + c*d rounded as two products and one sum, never fused: the result is
 // the same when the two pairs are swapped, which keeps every kernel's
 // rounding invariant under the x <-> y transposition of the data.
@@ -129,8 +146,8 @@ __device__ __forceinline__ void rusanov(const R qL[4], const R qR[4], R gam, R g
   R fL[4], fR[4], unL, pL, irL, unR, pR, irR;
   euler_flux<AX>(qL, gm1, fL, unL, pL, irL);
   euler_flux<AX>(qR, gm1, fR, unR, pR, irR);
-  const R lL = fabs(unL) + sqrt(gam * pL * irL);
-  const R lR = fabs(unR) + sqrt(gam * pR * irR);
+  const R lL = fabs(unL) + sqrt_pos(gam * pL * irL);
+  const R lR = fabs(unR) + sqrt_pos(gam * pR * irR);
   const R lam = (lL >= lR) ? lL : lR;
 #pragma unroll
   for (int k = 0; k < 4; ++k) Fh[k] = r_fma(-(R(0.5) * lam), qR[k] - qL[k], R(0.5) * (fL[k] + fR[k]));

@@ -64,7 +64,7 @@ __device__ __forceinline__ void rusanov_vjp(const R qL[4], const R qR[4], const 
   const R irL = R(1) / qL[0], irR = R(1) / qR[0];
   const R pL = gm1 * (qL[3] - R(0.5) * (qL[1] * qL[1] + qL[2] * qL[2]) * irL);
   const R pR = gm1 * (qR[3] - R(0.5) * (qR[1] * qR[1] + qR[2] * qR[2]) * irR);
-  const R cLs = sqrt(gam * pL * irL), cRs = sqrt(gam * pR * irR);
+  const R cLs = sqrt_pos(gam * pL * irL), cRs = sqrt_pos(gam * pR * irR);
   const R lL = fabs(qL[n] * irL) + cLs, lR = fabs(qR[n] * irR) + cRs;
   const R lam = lL >= lR ? lL : lR;
   const bool tie = fabs(lL - lR) <= R(1e-12) * lam;
