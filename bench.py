@@ -144,6 +144,114 @@ def cpu_baseline(P=3, n=256, steps=None, budget_s=15.0):
     }
 
 
+def copy_bandwidth(reps=5):
+    """Device-to-device copy of 1 GiB (read 1 GiB + write 1 GiB), median of
+    reps, in GB/s: the practical HBM ceiling next to the 8 TB/s peak."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    ts.sort()
+    del src, dst
+    return 2.0 * n * 8 / ts[len(ts) // 2] / 1e9
+
+
+def small_config():
+    """P=2 vortex on 20x20 elements, dt=1e-3, 100 steps: launch-latency
+    regime (14400 unknowns)."""
+    from paper_1709_01619_amd import Solver
+    s = Solver(2, 20, 20)
+    q = vortex_state(s)
+    ms = time_steps(s, q, 1e-3, 100, 5)
+    return {"workload": "P=2 vortex 20x20, dt=1e-3, 100 steps", "ms_per_step": ms,
+            "dof_updates_per_s": 3.0 * s.n_unknowns / (ms * 1e-3)}
+
+
+def limited_riemann():
+    """P=2 four-quadrant Riemann problem on 512x512 transmissive elements,
+    TVB characteristic limiter (M=10) after every stage, device CFL dt at
+    CFL 0.1, to t=0.3: steps, time per step, troubled fraction at t=0.3 and
+    the largest deviation from the problem's diagonal symmetry."""
+    import torch
+    import inputs
+    from paper_1709_01619_amd import Solver
+    n = 512
+    s = Solver(2, n, n, 0.0, 1.0, 0.0, 1.0, bc="transmissive", limiter=True, tvb_m=10.0,
+               cfl=0.1, t_end=0.3)
+    x, y = s.coords()
+    q = torch.from_numpy(inputs.riemann_quadrants(x.cpu().numpy(), y.cpu().numpy())).cuda()
+    s.set_time(0.0)
+    s.limit(q)
+    s.troubled_total(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps, t = 0, 0.0
+    while t < 0.29 and steps < 20000:      # chunks of 100 well before t_end
+        for _ in range(100):
+            s.step(q, 0.0, limit=True)
+        steps += 100
+        t, _ = s.get_time()
+    while t < 0.3 * (1 - 1e-14) and steps < 20000:   # then one at a time, to count exactly
+        s.step(q, 0.0, limit=True)
+        steps += 1
+        t, _ = s.get_time()
+    el = time.perf_counter() - t0
+    ndone = steps
+    total = s.troubled_total()
+    qt = q[[0, 2, 1, 3]].permute(0, 2, 1, 4, 3)
+    sym = float((q - qt).abs().max().item())
+    return {"workload": "P=2 Riemann 512x512 transmissive, TVB M=10 after every stage, "
+                        "CFL 0.1 device dt, to t=0.3",
+            "steps": ndone, "t_final": t, "s_per_step": el / ndone,
+            "troubled_element_passes": total,
+            "troubled_fraction_mean": total / (3.0 * ndone * n * n),
+            "troubled_note": "troubled elements summed over all limiter passes (3 per step) / "
+                             "(passes x elements)",
+            "diagonal_symmetry_max_dev": sym}
+
+
+def adjoint_p4():
+    """P=4 vortex on 1024x1024 (104.9M unknowns): 200 steps of dt=1e-4,
+    checkpoint every 20, forward and backward, FP64 and FP32-bulk."""
+    import torch
+    import inputs
+    from paper_1709_01619_amd import Rollout, Solver
+    out = {"workload": "P=4 vortex 1024x1024, 200 steps dt=1e-4, checkpoint 20"}
+    for prec in ("fp64", "fp32_bulk"):
+        s = Solver(4, 1024, 1024, precision=prec)
+        x, y = s.coords()
+        V = inputs.Vortex()
+        q0 = vortex_state(s).requires_grad_(True)
+        rho_ex = torch.from_numpy(V.conserved(x.cpu().numpy(), y.cpu().numpy(), 0.02)[0]).cuda()
+        del x, y
+        W = s.quad_weights()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qT = Rollout.apply(q0, s, 1e-4, 200, 20)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J = 0.5 * ((qT[0] - rho_ex) ** 2 * W).sum()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out[prec] = {"forward_s_per_step": (t1 - t0) / 200, "backward_s_per_step": (t2 - t1) / 200,
+                     "adjoint_s_per_step": (t2 - t0) / 200}
+        log("adjoint p4", prec, out[prec])
+        del s, q0, qT, J, rho_ex
+        torch.cuda.empty_cache()
+    return out
+
+
 def profile_legs(a):
     """Run selected legs only (used under rocprofv3): no JSON line."""
     import torch
@@ -303,6 +411,18 @@ def main(argv=None):
             log("p4 1024", prec, scale[prec])
             del s, q
 
+    extra = {}
+    if not a.quick:
+        extra["c1_small"] = small_config()
+        log("c1", extra["c1_small"])
+        extra["c3_limited_riemann"] = limited_riemann()
+        log("c3", extra["c3_limited_riemann"])
+        extra["c5_adjoint"] = adjoint_p4()
+    copy_gbs = copy_bandwidth()
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log("copy", copy_gbs)
+
     cpu = None
     if not a.no_cpu:
         log("cpu baseline (oracle) ...")
@@ -334,6 +454,7 @@ def main(argv=None):
         "l2_error_t10": l2,
         "adjoint": adj,
         "scale_p4_1024": scale,
+        **extra,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -172,6 +172,14 @@ cpr_status cpr_tables(int32_t order_p, double* xi, double* w, double* gLp, doubl
 cpr_status cpr_set_time(cpr_ctx* ctx, double t);
 cpr_status cpr_get_time(cpr_ctx* ctx, double* t_host, double* last_dt_host);
 
+/* Number of troubled-element detections summed over every limiter pass of
+ * the context (cpr_limit calls and the passes inside cpr_rk3_step) since
+ * cpr_init or the last reset: the limiter activity of Section 2.6's
+ * detection step, e.g. the troubled fraction of a run is
+ * total / (passes x nx x ny). Synchronises; stores the count in
+ * *total_host; reset != 0 clears the total after reading. */
+cpr_status cpr_troubled_total(cpr_ctx* ctx, int64_t* total_host, int32_t reset);
+
 /* Wait for the context's stream; return any deferred device error. */
 cpr_status cpr_sync(cpr_ctx* ctx);
 

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_double, c_int32, c_void_p
+from ctypes import POINTER, c_double, c_int32, c_int64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpr.so")
@@ -24,7 +24,7 @@ CPR_LIM_NONE, CPR_LIM_TVB_CHAR = 0, 1
 SYMBOLS = (
     "cpr_init", "cpr_destroy", "cpr_set_stream", "cpr_residual", "cpr_rk3_step", "cpr_limit",
     "cpr_residual_vjp", "cpr_adjoint_step", "cpr_max_wavespeed", "cpr_integrals", "cpr_l2_diff",
-    "cpr_point_coords", "cpr_tables", "cpr_set_time", "cpr_get_time", "cpr_sync",
+    "cpr_point_coords", "cpr_tables", "cpr_set_time", "cpr_get_time", "cpr_troubled_total", "cpr_sync",
     "cpr_status_string", "cpr_last_error",
 )
 
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
         "cpr_tables": (c_int32, [c_int32, P(c_double), P(c_double), P(c_double), P(c_double)]),
         "cpr_set_time": (c_int32, [c_void_p, c_double]),
         "cpr_get_time": (c_int32, [c_void_p, P(c_double), P(c_double)]),
+        "cpr_troubled_total": (c_int32, [c_void_p, P(c_int64), c_int32]),
         "cpr_sync": (c_int32, [c_void_p]),
         "cpr_status_string": (ctypes.c_char_p, [c_int32]),
         "cpr_last_error": (ctypes.c_char_p, [c_void_p]),

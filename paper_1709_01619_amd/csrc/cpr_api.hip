@@ -24,9 +24,11 @@ struct cpr_ctx {
   double* lam1;    // adjoint stage cotangents
   double* lam2;
   double* qbar;    // element means (limiter)
-  int* iscr;       // [0] error flag, [1] skip flag, [2] troubled count, [3..4] lam bits
+  int* iscr;       // [0] error flag, [1] skip flag, [2] troubled count, [4..5] lam bits,
+                   // [6..7] helper max bits, [8..9] troubled running total
   double* dscal;   // [0] t, [1] dt
   unsigned long long* lam_bits;
+  unsigned long long* troubled_total;
   double* partials;
   double* red_out;  // 4 doubles
   char last_error[512];
@@ -101,6 +103,7 @@ cpr_status limit_pass(cpr_ctx* c, double* q, int* flags, int* count, bool device
   l.qbar = c->qbar;
   l.flags = flags;
   l.count = count;
+  l.total = c->troubled_total;
   l.tvb_m = c->cfg.tvb_m;
   l.skip = device_dt ? c->iscr + 1 : nullptr;
   l.err = c->iscr;
@@ -205,11 +208,11 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   for (double** p : states)
     if (e == hipSuccess) e = hipMalloc(p, sb);
   if (e == hipSuccess) e = hipMalloc(&x->qbar, 4 * x->n_elem * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&x->iscr, 8 * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc(&x->iscr, 10 * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&x->dscal, 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&x->partials, reduce_partials_size(c.order_p, x->geo) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&x->red_out, 4 * sizeof(double));
-  if (e == hipSuccess) e = hipMemsetAsync(x->iscr, 0, 8 * sizeof(int), x->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(x->iscr, 0, 10 * sizeof(int), x->stream);
   if (e == hipSuccess) e = hipMemsetAsync(x->dscal, 0, 4 * sizeof(double), x->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
   if (e != hipSuccess) {
@@ -220,6 +223,7 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
     return st;
   }
   x->lam_bits = reinterpret_cast<unsigned long long*>(x->iscr + 4);
+  x->troubled_total = reinterpret_cast<unsigned long long*>(x->iscr + 8);
   *out = x;
   return CPR_OK;
 }
@@ -381,6 +385,17 @@ cpr_status cpr_get_time(cpr_ctx* ctx, double* t_host, double* last_dt_host) {
   cpr_status st = check_device_error(ctx);
   if (t_host) *t_host = v[0];
   if (last_dt_host) *last_dt_host = v[1];
+  return st;
+}
+
+cpr_status cpr_troubled_total(cpr_ctx* ctx, int64_t* total_host, int32_t reset) {
+  if (ctx == nullptr || total_host == nullptr) return CPR_EINVAL;
+  unsigned long long v = 0;
+  HIP_TRY(ctx, hipMemcpyAsync(&v, ctx->troubled_total, sizeof(v), hipMemcpyDeviceToHost, ctx->stream),
+          "read troubled total");
+  if (reset) HIP_TRY(ctx, launch_fill_int(ctx->iscr + 8, 0, 2, ctx->stream), "clear troubled total");
+  cpr_status st = check_device_error(ctx);
+  *total_host = (int64_t)v;
   return st;
 }
 

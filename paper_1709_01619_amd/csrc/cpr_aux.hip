@@ -200,6 +200,7 @@ __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, L
   if (A.flags != nullptr) A.flags[e] = troubled ? 1 : 0;
   if (!troubled) return;
   if (A.count != nullptr) atomicAdd(A.count, 1);
+  if (A.total != nullptr) atomicAdd(A.total, 1ull);
   const double hx = 0.5 * G.dx, hy = 0.5 * G.dy;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {

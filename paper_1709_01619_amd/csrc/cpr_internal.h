@@ -72,6 +72,7 @@ struct LimitArgs {
   double* qbar;     // 4 * ny * nx scratch
   int* flags;       // nullable, ny * nx
   int* count;       // nullable device counter (atomic add of troubled elements)
+  unsigned long long* total;  // nullable running total of troubled elements
   double tvb_m;
   const int* skip;  // nullable
   int* err;

@@ -9,7 +9,7 @@ GPU raises.
 from __future__ import annotations
 
 import ctypes
-from ctypes import byref, c_double, c_int32, c_void_p
+from ctypes import byref, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
 
@@ -197,6 +197,15 @@ class Solver:
         self._enter()
         self._check(self.lib.cpr_get_time(self._ctx, byref(t), byref(dt)), "cpr_get_time")
         return float(t.value), float(dt.value)
+
+    def troubled_total(self, reset=False):
+        """Troubled elements summed over every limiter pass since the last
+        reset (synchronises)."""
+        n = c_int64(0)
+        self._enter()
+        self._check(self.lib.cpr_troubled_total(self._ctx, byref(n), 1 if reset else 0),
+                    "cpr_troubled_total")
+        return int(n.value)
 
     def sync(self):
         self._enter()

@@ -78,7 +78,13 @@ def test_limited_rk3_riemann_steps_match_oracle():
     x, y = g.coords()
     q = inputs.riemann_quadrants(x, y)
     say("limited rk3 riemann")
-    lim = lambda z: limiter.limit(z, g, M=10.0)
+    flagged = [0]
+
+    def lim(z):
+        out, fl = limiter.limit(z, g, M=10.0, return_flags=True)
+        flagged[0] += int(fl.sum())
+        return out
+
     s = make_solver(g, limiter=True, tvb_m=10.0)
     qo = lim(q)
     qd = dev(q)
@@ -89,6 +95,11 @@ def test_limited_rk3_riemann_steps_match_oracle():
         qo = cpr.rk3_step(qo, dt, g, limit=lim)
         s.step(qd, dt, limit=True)
     assert rel_err(host(qd), qo) <= 1e-11
+    # the running total counts every pass: the initial one and 3 per step
+    assert flagged[0] > 0
+    assert s.troubled_total() == flagged[0]
+    assert s.troubled_total(reset=True) == flagged[0]
+    assert s.troubled_total() == 0
     # diagonal symmetry of the GPU result
     qg = host(qd)
     qt = qg[[0, 2, 1, 3]].transpose(0, 2, 1, 4, 3)
