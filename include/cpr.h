@@ -67,7 +67,8 @@ enum { CPR_LIM_NONE = 0, CPR_LIM_TVB_CHAR = 1 };
 typedef struct {
   int32_t abi_version;  /* must equal CPR_ABI_VERSION                     */
   int32_t order_p;      /* polynomial degree P, 1..4                      */
-  int32_t nx, ny;       /* elements per direction, >= 1                   */
+  int32_t nx, ny;       /* elements per direction, 1..2^20 each, and
+                           nx*ny <= 2^29                                  */
   double x0, x1;        /* domain [x0,x1] x [y0,y1], x1 > x0, y1 > y0     */
   double y0, y1;
   int32_t bc;           /* CPR_BC_PERIODIC or CPR_BC_TRANSMISSIVE         */

@@ -165,6 +165,8 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   if (c.abi_version != CPR_ABI_VERSION) return CPR_EINVAL;
   if (c.order_p < 1 || c.order_p > kMaxP) return CPR_EINVAL;
   if (c.nx < 1 || c.ny < 1 || c.nx > (1 << 20) || c.ny > (1 << 20)) return CPR_EINVAL;
+  // element means are indexed k*nx*ny + e in 32-bit arithmetic
+  if ((int64_t)c.nx * c.ny > ((int64_t)1 << 29)) return CPR_EINVAL;
   if (!(std::isfinite(c.x0) && std::isfinite(c.x1) && c.x1 > c.x0)) return CPR_EINVAL;
   if (!(std::isfinite(c.y0) && std::isfinite(c.y1) && c.y1 > c.y0)) return CPR_EINVAL;
   if (c.bc != CPR_BC_PERIODIC && c.bc != CPR_BC_TRANSMISSIVE) return CPR_EINVAL;

@@ -55,12 +55,21 @@ def test_config_struct_layout_matches_header():
     ("abi_version", 99), ("order_p", 0), ("order_p", 5), ("nx", 0), ("ny", -3),
     ("x1", 0.0), ("y1", -1.0), ("bc", 7), ("precision", 3), ("gamma", 1.0),
     ("gamma", float("nan")), ("limiter", 2), ("reserved0", 1), ("tvb_m", -1.0), ("cfl", -0.1),
-    ("t_end", float("inf")),
+    ("t_end", float("inf")), ("nx", (1 << 20) + 1),
 ])
 def test_init_rejects_invalid_config_without_gpu(field, value):
     L, lib = _lib()
     cfg = L.make_config(2, 4, 4)
     setattr(cfg, field, value)
+    ctx = c_void_p()
+    assert lib.cpr_init(byref(cfg), None, byref(ctx)) == L.CPR_EINVAL
+    assert not ctx.value
+
+
+def test_init_rejects_too_many_elements_without_gpu():
+    """nx*ny is capped at 2^29 (each side may reach 2^20)."""
+    L, lib = _lib()
+    cfg = L.make_config(2, 1 << 15, (1 << 14) + 1)
     ctx = c_void_p()
     assert lib.cpr_init(byref(cfg), None, byref(ctx)) == L.CPR_EINVAL
     assert not ctx.value
