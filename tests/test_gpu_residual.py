@@ -16,7 +16,8 @@ from tests.gpu_util import dev, host, make_solver, rel_err, say, torch
 
 pytestmark = pytest.mark.gpu
 
-MESHES = [(1, 1), (2, 2), (3, 5), (8, 8), (9, 8), (13, 11), (17, 3), (20, 20)]
+MESHES = [(1, 1), (2, 2), (3, 5), (8, 8), (9, 8), (13, 11), (17, 3), (20, 20), (1, 17), (23, 1),
+          (33, 2)]
 
 
 @pytest.mark.parametrize("bc", ["periodic", "transmissive"])
