@@ -18,6 +18,14 @@ points:
     polynomial.
 Boundaries: periodic wrap, or transmissive (the outside state equals the
 inside extrapolated state, so the face flux is F(q_inside)).
+
+Scheme "gll_chain" is the paper's own CPR (Section 2.2 with Gauss-Lobatto
+solution points; the chain-rule divergence of its CPR flux kernel,
+Algorithms 7 and 8): the face states and face fluxes are the end values of
+each line, and Pi[div F] is the chain rule A(q) dq/dx + B(q) dq/dy at every solution point, with dq/dx the
+derivative of the solution polynomial. The correction term is unchanged. The
+chain rule does not telescope, so this scheme is not discretely
+conservative for the nonlinear fluxes.
 """
 
 from __future__ import annotations
@@ -30,6 +38,8 @@ from . import euler, tables
 
 PERIODIC = "periodic"
 TRANSMISSIVE = "transmissive"
+GL_LP = "gl_lp"          # Gauss-Legendre points, derivative of the flux interpolant
+GLL_CHAIN = "gll_chain"  # Gauss-Lobatto points, chain-rule divergence (the paper's CPR)
 
 
 @dataclass(frozen=True)
@@ -43,6 +53,7 @@ class Grid:
     y1: float = 10.0
     bc: str = PERIODIC
     gamma: float = 1.4
+    scheme: str = GL_LP
 
     def __post_init__(self):
         if not (1 <= self.P <= 8):
@@ -55,6 +66,8 @@ class Grid:
             raise ValueError(f"unknown boundary condition {self.bc}")
         if not self.gamma > 1.0:
             raise ValueError("gamma must exceed 1")
+        if self.scheme not in (GL_LP, GLL_CHAIN):
+            raise ValueError(f"unknown scheme {self.scheme}")
 
     @property
     def n1(self):
@@ -77,7 +90,7 @@ class Grid:
         return 4 * self.ny * self.nx * self.n1 * self.n1
 
     def tables(self):
-        return tables.get(self.P)
+        return tables.get(self.P, "gll" if self.scheme == GLL_CHAIN else "gl")
 
     def coords(self):
         """Physical coordinates (x, y), each of shape (ny, nx, n1, n1), of the
@@ -145,8 +158,17 @@ def residual(q, grid: Grid):
     f = euler.flux_x(q, g)
     gf = euler.flux_y(q, g)
 
+    chain = grid.scheme == GLL_CHAIN
+    if chain:
+        A = euler.flux_jacobian(q, g, 0)                 # (4, 4, ny, nx, n1, n1)
+        B = euler.flux_jacobian(q, g, 1)
+
     # x direction (xi, last axis)
-    dfdxi = np.einsum("il,kJIjl->kJIji", T.D, f)
+    if chain:
+        dqdxi = np.einsum("il,kJIjl->kJIji", T.D, q)
+        dfdxi = np.einsum("abJIji,bJIji->aJIji", A, dqdxi)
+    else:
+        dfdxi = np.einsum("il,kJIjl->kJIji", T.D, f)
     fW = f @ T.em
     fE = f @ T.ep
     left, right = _x_face_states(q, grid)
@@ -156,7 +178,11 @@ def residual(q, grid: Grid):
     Rx = dfdxi + (FW - fW)[..., None] * T.gLp + (FE - fE)[..., None] * T.gRp
 
     # y direction (eta, second-last axis)
-    dgdeta = np.einsum("jl,kJIli->kJIji", T.D, gf)
+    if chain:
+        dqdeta = np.einsum("jl,kJIli->kJIji", T.D, q)
+        dgdeta = np.einsum("abJIji,bJIji->aJIji", B, dqdeta)
+    else:
+        dgdeta = np.einsum("jl,kJIli->kJIji", T.D, gf)
     gS = np.einsum("l,kJIli->kJIi", T.em, gf)
     gN = np.einsum("l,kJIli->kJIi", T.ep, gf)
     below, above = _y_face_states(q, grid)

@@ -6,9 +6,11 @@ flux polynomial at those points, and (iii) a correction polynomial built from
 Radau polynomials that lifts the interface flux jump (the DG-equivalent
 choice). Tensor products of these 1D tables give the 2D quad element.
 
-Solution points are Gauss-Legendre nodes (the interpolating flux points sit
-on the element faces, so face values are extrapolated from the nodal
-polynomial).
+Two point sets. Gauss-Legendre nodes ("gl", the default): the flux points
+on the element faces are not solution points, so face values are
+extrapolated from the nodal polynomial. Gauss-Lobatto-Legendre nodes ("gll",
+the paper's own choice in Section 2.2): the end points are solution points,
+so the face value of a line is its end value and no interpolation is needed.
 """
 
 from __future__ import annotations
@@ -85,11 +87,28 @@ def radau_right_coeffs(P: int) -> np.ndarray:
     return c
 
 
-def build(P: int) -> Tables:
+def lobatto_nodes_weights(P: int):
+    """Gauss-Lobatto-Legendre rule with P+1 points: -1, the P-1 roots of
+    L_P', +1; weights 2 / (P (P+1) L_P(x)^2) (exact to degree 2P-1)."""
+    cP = np.zeros(P + 1)
+    cP[P] = 1.0
+    inner = npleg.legroots(npleg.legder(cP)) if P >= 2 else np.zeros(0)
+    xi = np.concatenate([[-1.0], np.sort(np.real(inner)), [1.0]])
+    LP = npleg.legval(xi, cP)
+    w = 2.0 / (P * (P + 1) * LP * LP)
+    return xi, w
+
+
+def build(P: int, points: str = "gl") -> Tables:
     if not (1 <= P <= 8):
         raise ValueError(f"P must be in [1, 8], got {P}")
     n1 = P + 1
-    xi, w = npleg.leggauss(n1)
+    if points == "gl":
+        xi, w = npleg.leggauss(n1)
+    elif points == "gll":
+        xi, w = lobatto_nodes_weights(P)
+    else:
+        raise ValueError(f"unknown point set {points}")
     D = lagrange_deriv(xi, xi)
     em = lagrange_eval(xi, -1.0)[0]
     ep = lagrange_eval(xi, 1.0)[0]
@@ -98,10 +117,10 @@ def build(P: int) -> Tables:
     return Tables(P=P, xi=xi, w=w, D=D, em=em, ep=ep, gLp=gLp, gRp=gRp)
 
 
-_CACHE: dict[int, Tables] = {}
+_CACHE: dict = {}
 
 
-def get(P: int) -> Tables:
-    if P not in _CACHE:
-        _CACHE[P] = build(P)
-    return _CACHE[P]
+def get(P: int, points: str = "gl") -> Tables:
+    if (P, points) not in _CACHE:
+        _CACHE[(P, points)] = build(P, points)
+    return _CACHE[(P, points)]

@@ -1,8 +1,11 @@
 """Brute-force CPR residual at 50 digits with mpmath, written directly from
-the definitions (no tables): Gauss-Legendre nodes as roots of L_{P+1} found
-by mpmath, Lagrange polynomials as products, Radau correction polynomials
-from mpmath's Legendre functions, and the derivative of the corrected flux
-polynomial by mpmath's numerical differentiation. Used only to pin the
+the definitions (no tables): Gauss-Legendre nodes as roots of L_{P+1} (or
+Gauss-Lobatto nodes: -1, +1 and the roots of L_P') found by mpmath, Lagrange
+polynomials as products, Radau correction polynomials from mpmath's Legendre
+functions, and derivatives by mpmath's numerical differentiation: of the
+corrected flux polynomial (scheme gl_lp), or, for the chain rule (scheme
+gll_chain), of the solution polynomial, pushed through the flux as a
+directional derivative d/ds F(q + s dq) at s = 0. Used only to pin the
 oracle on tiny meshes; it shares nothing with the oracle."""
 
 import mpmath as mp
@@ -13,6 +16,19 @@ def gl_nodes(n):
     for k in range(n):
         x0 = mp.cos(mp.pi * (k + mp.mpf(3) / 4) / (n + mp.mpf(1) / 2))
         xs.append(mp.findroot(lambda x: mp.legendre(n, x), x0))
+    return sorted(xs)
+
+
+def gll_nodes(n):
+    P = n - 1
+
+    def dL(x):
+        return mp.diff(lambda t: mp.legendre(P, t), x)
+
+    xs = [mp.mpf(-1), mp.mpf(1)]
+    for k in range(1, P):
+        x0 = -mp.cos(mp.pi * k / P)
+        xs.append(mp.findroot(dL, x0))
     return sorted(xs)
 
 
@@ -46,13 +62,13 @@ def rusanov(qL, qR, g, axis):
     return [(fL[k] + fR[k]) / 2 - lam * (qR[k] - qL[k]) / 2 for k in range(4)]
 
 
-def residual(q, P, nx, ny, x0, x1, y0, y1, bc, gamma, dps=50):
+def residual(q, P, nx, ny, x0, x1, y0, y1, bc, gamma, dps=50, scheme="gl_lp"):
     """q: nested sequence q[k][J][I][j][i] of floats. Returns the same
     nesting of mpf residuals."""
     mp.mp.dps = dps
     g = mp.mpf(gamma)
     n1 = P + 1
-    nodes = gl_nodes(n1)
+    nodes = gll_nodes(n1) if scheme == "gll_chain" else gl_nodes(n1)
     dx = (mp.mpf(x1) - mp.mpf(x0)) / nx
     dy = (mp.mpf(y1) - mp.mpf(y0)) / ny
 
@@ -123,7 +139,16 @@ def residual(q, P, nx, ny, x0, x1, y0, y1, bc, gamma, dps=50):
                             return fpoly(x) + jl * gL(x) + jh * gR(x)
 
                         for a in range(n1):
-                            d = mp.diff(corrected, nodes[a])
+                            if scheme == "gll_chain":
+                                qa = pts[a]
+                                dq = [mp.diff(lambda x, m=m: extrap(pts, x)[m], nodes[a])
+                                      for m in range(4)]
+                                dF = mp.diff(lambda s, k=k: flux([qa[m] + s * dq[m]
+                                                                  for m in range(4)], g, axis)[k], 0)
+                                d = (dF + jl * mp.diff(gL, nodes[a])
+                                     + jh * mp.diff(gR, nodes[a]))
+                            else:
+                                d = mp.diff(corrected, nodes[a])
                             if axis == 0:
                                 R[k][J][I][c][a] -= 2 * d / h
                             else:
