@@ -9,11 +9,20 @@
  * form, Section 2.6 for the slope limiter, Section 4 for the Rusanov flux,
  * the three-stage Runge-Kutta scheme and the CFL condition).
  *
- * Discretisation: P+1 Gauss-Legendre solution points per direction per
- * element; face states extrapolated from each element's solution
- * polynomial; Rusanov common flux at face points; Radau (DG-equivalent)
- * correction lift; divergence of the degree-P flux interpolant; SSP-RK3 in
- * Shu-Osher form.
+ * Discretisation (scheme CPR_SCHEME_GL_LP, the default): P+1
+ * Gauss-Legendre solution points per direction per element; face states
+ * extrapolated from each element's solution polynomial; Rusanov common flux
+ * at face points; Radau (DG-equivalent) correction lift; divergence of the
+ * degree-P flux interpolant; SSP-RK3 in Shu-Osher form. This scheme is
+ * exactly conservative.
+ *
+ * Scheme CPR_SCHEME_GLL_CHAIN is the paper's own CPR (Section 2.2, Fig. 1(b),
+ * and the CPR flux kernel of Algorithms 7 and 8): P+1 Gauss-Lobatto
+ * solution points, so the face states are the end values of each line; the
+ * divergence is the chain rule A(q) dq/dx + B(q) dq/dy with dq/dx the
+ * derivative of the solution polynomial; the same Rusanov flux and Radau
+ * lift. The chain rule does not telescope, so this scheme conserves mass
+ * exactly but momentum and energy only to truncation error.
  *
  * State layout (every q, r, v, lambda buffer): contiguous float64 (float32
  * for the FP32-bulk residual output) array q[k][J][I][j][i] of
@@ -22,7 +31,9 @@
  *   J in 0..ny-1 element row (y), I in 0..nx-1 element column (x),
  *   j in 0..P  eta index, i in 0..P xi index of the solution point.
  * Solution point (I,J,i,j) sits at x = x0 + (I + 1/2 + xi_i/2) dx,
- * y = y0 + (J + 1/2 + xi_j/2) dy with xi the ascending Gauss-Legendre nodes.
+ * y = y0 + (J + 1/2 + xi_j/2) dy with xi the ascending nodes of the
+ * context's point set (Gauss-Legendre, or Gauss-Lobatto for
+ * CPR_SCHEME_GLL_CHAIN).
  *
  * Ownership: all array arguments are device pointers owned by the caller
  * (unless documented as host pointers). The library owns its scratch,
@@ -63,6 +74,7 @@ typedef enum {
 enum { CPR_BC_PERIODIC = 0, CPR_BC_TRANSMISSIVE = 1 };
 enum { CPR_FP64 = 0, CPR_FP32_BULK = 1 };
 enum { CPR_LIM_NONE = 0, CPR_LIM_TVB_CHAR = 1 };
+enum { CPR_SCHEME_GL_LP = 0, CPR_SCHEME_GLL_CHAIN = 1 };
 
 typedef struct {
   int32_t abi_version;  /* must equal CPR_ABI_VERSION                     */
@@ -77,14 +89,15 @@ typedef struct {
                            sums and norms in float64                     */
   double gamma;         /* ratio of specific heats, > 1                   */
   int32_t limiter;      /* CPR_LIM_NONE or CPR_LIM_TVB_CHAR               */
-  int32_t reserved0;    /* must be 0                                      */
+  int32_t scheme;       /* CPR_SCHEME_GL_LP or CPR_SCHEME_GLL_CHAIN       */
   double tvb_m;         /* TVB constant M >= 0 (limiter only)             */
   double cfl;           /* CFL number for device-computed dt, > 0         */
   double t_end;         /* final time for device-computed dt (clips the
                            last step); <= 0 means no clipping            */
 } cpr_config;
 
-/* Create a context (Section 2.2 tables for degree P, scratch for the RK
+/* Create a context (Section 2.2 tables for degree P on the scheme's point
+ * set, scratch for the RK
  * stages, the limiter and the adjoint). stream: a hipStream_t, or NULL for
  * the null stream. Returns CPR_EINVAL for an invalid configuration or NULL
  * cfg/out, CPR_ENOMEM if scratch cannot be allocated (nothing leaks). */
@@ -99,8 +112,9 @@ cpr_status cpr_set_stream(cpr_ctx* ctx, void* stream);
 
 /* r = R(q) = dq/dt of the CPR semi-discretisation (Section 2.2, the
  * differential form with the Radau correction; Rusanov face flux of
- * Section 4). q: device float64 state. r: device buffer of the same shape,
- * float64 (CPR_FP64) or float32 (CPR_FP32_BULK); r must not alias q. */
+ * Section 4) in the context's scheme. q: device float64 state. r: device
+ * buffer of the same shape, float64 (CPR_FP64) or float32 (CPR_FP32_BULK);
+ * r must not alias q. */
 cpr_status cpr_residual(cpr_ctx* ctx, const double* q, void* r);
 
 /* Advance q (device, in place) by one SSP-RK3 step of size dt in Shu-Osher
@@ -131,7 +145,7 @@ cpr_status cpr_limit(cpr_ctx* ctx, double* q, int32_t* flags, int32_t* n_trouble
  * sides' gradients is used). In CPR_FP32_BULK contexts the transpose is
  * evaluated in float32 (as the residual is) and its two sweep parts are
  * summed in float64. q, v, out: device float64 states; out must not alias
- * q or v. */
+ * q or v. CPR_EUNSUPPORTED for a CPR_SCHEME_GLL_CHAIN context. */
 cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, double* out);
 
 /* Discrete adjoint of one unlimited SSP-RK3 step of size dt > 0 from q_n:
@@ -141,7 +155,8 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
  * All pointers device float64 states; lam_n may alias lam_np1. In
  * CPR_FP32_BULK contexts the stage states are recomputed with the float32
  * residual and the J^T products are float32 (cpr_residual_vjp); the lam
- * combinations are float64. CPR_EUNSUPPORTED on a context with a limiter. */
+ * combinations are float64. CPR_EUNSUPPORTED on a context with a limiter
+ * or with CPR_SCHEME_GLL_CHAIN. */
 cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt,
                             const double* lam_np1, double* lam_n);
 
@@ -149,8 +164,8 @@ cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt,
  * synchronises; result to *out_host. */
 cpr_status cpr_max_wavespeed(cpr_ctx* ctx, const double* q, double* out_host);
 
-/* Domain integrals of the four conserved variables by the tensor
- * Gauss-Legendre rule, sum w_i w_j (dx dy / 4) q; synchronises;
+/* Domain integrals of the four conserved variables by the tensor rule of
+ * the context's point set, sum w_i w_j (dx dy / 4) q; synchronises;
  * out_host[4] (host). */
 cpr_status cpr_integrals(cpr_ctx* ctx, const double* q, double* out_host);
 
@@ -166,8 +181,17 @@ cpr_status cpr_point_coords(cpr_ctx* ctx, double* x, double* y);
 
 /* The library's 1D tables for degree P (host arrays of P+1 values, any may
  * be NULL): Gauss-Legendre nodes and weights, and the Radau correction
- * derivatives gL'(xi_i), gR'(xi_i). No context or device needed. */
+ * derivatives gL'(xi_i), gR'(xi_i). No context or device needed.
+ * CPR_EINVAL for P outside 1..4. */
 cpr_status cpr_tables(int32_t order_p, double* xi, double* w, double* gLp, double* gRp);
+
+/* The same tables for a scheme's point set: CPR_SCHEME_GL_LP as
+ * cpr_tables; CPR_SCHEME_GLL_CHAIN the Gauss-Lobatto-Legendre nodes (-1, the
+ * roots of L_P', +1), weights 2 / (P (P+1) L_P(xi)^2), and the Radau
+ * correction derivatives at those nodes (Section 2.2). No context or device
+ * needed. CPR_EINVAL for an unknown scheme or P outside 1..4. */
+cpr_status cpr_scheme_tables(int32_t scheme, int32_t order_p, double* xi, double* w, double* gLp,
+                             double* gRp);
 
 /* Device time of the CFL-driven stepping (cpr_rk3_step with dt <= 0). */
 cpr_status cpr_set_time(cpr_ctx* ctx, double t);

@@ -19,12 +19,13 @@ CPR_OK, CPR_EINVAL, CPR_ENOMEM, CPR_EHIP, CPR_EUNSUPPORTED, CPR_ENONPHYSICAL = 0
 CPR_BC_PERIODIC, CPR_BC_TRANSMISSIVE = 0, 1
 CPR_FP64, CPR_FP32_BULK = 0, 1
 CPR_LIM_NONE, CPR_LIM_TVB_CHAR = 0, 1
+CPR_SCHEME_GL_LP, CPR_SCHEME_GLL_CHAIN = 0, 1
 
 # exported symbols declared in include/cpr.h
 SYMBOLS = (
     "cpr_init", "cpr_destroy", "cpr_set_stream", "cpr_residual", "cpr_rk3_step", "cpr_limit",
     "cpr_residual_vjp", "cpr_adjoint_step", "cpr_max_wavespeed", "cpr_integrals", "cpr_l2_diff",
-    "cpr_point_coords", "cpr_tables", "cpr_set_time", "cpr_get_time", "cpr_troubled_total", "cpr_sync",
+    "cpr_point_coords", "cpr_tables", "cpr_scheme_tables", "cpr_set_time", "cpr_get_time", "cpr_troubled_total", "cpr_sync",
     "cpr_status_string", "cpr_last_error",
 )
 
@@ -43,7 +44,7 @@ class CprConfig(ctypes.Structure):
         ("precision", c_int32),
         ("gamma", c_double),
         ("limiter", c_int32),
-        ("reserved0", c_int32),
+        ("scheme", c_int32),
         ("tvb_m", c_double),
         ("cfl", c_double),
         ("t_end", c_double),
@@ -84,6 +85,8 @@ def load(path: str = LIB_PATH):
         "cpr_l2_diff": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(c_double)]),
         "cpr_point_coords": (c_int32, [c_void_p, c_void_p, c_void_p]),
         "cpr_tables": (c_int32, [c_int32, P(c_double), P(c_double), P(c_double), P(c_double)]),
+        "cpr_scheme_tables": (c_int32, [c_int32, c_int32, P(c_double), P(c_double), P(c_double),
+                                        P(c_double)]),
         "cpr_set_time": (c_int32, [c_void_p, c_double]),
         "cpr_get_time": (c_int32, [c_void_p, P(c_double), P(c_double)]),
         "cpr_troubled_total": (c_int32, [c_void_p, P(c_int64), c_int32]),
@@ -113,14 +116,18 @@ def check(status, ctx=None, what=""):
 
 def make_config(P, nx, ny, x0=0.0, x1=10.0, y0=0.0, y1=10.0, bc=CPR_BC_PERIODIC,
                 precision=CPR_FP64, gamma=1.4, limiter=CPR_LIM_NONE, tvb_m=10.0, cfl=0.0,
-                t_end=0.0):
+                t_end=0.0, scheme=CPR_SCHEME_GL_LP):
     return CprConfig(CPR_ABI_VERSION, P, nx, ny, x0, x1, y0, y1, bc, precision, gamma,
-                     limiter, 0, tvb_m, cfl, t_end)
+                     limiter, scheme, tvb_m, cfl, t_end)
 
 
-def tables(P):
-    """(xi, w, gL', gR') from the library's own table builder."""
+def tables(P, scheme=None):
+    """(xi, w, gL', gR') from the library's own table builder: cpr_tables,
+    or cpr_scheme_tables when a scheme is given."""
     lib = load()
     arrs = [(c_double * (P + 1))() for _ in range(4)]
-    check(lib.cpr_tables(P, *arrs), what="cpr_tables")
+    if scheme is None:
+        check(lib.cpr_tables(P, *arrs), what="cpr_tables")
+    else:
+        check(lib.cpr_scheme_tables(scheme, P, *arrs), what="cpr_scheme_tables")
     return tuple([a[i] for i in range(P + 1)] for a in arrs)

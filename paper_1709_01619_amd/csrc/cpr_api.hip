@@ -147,8 +147,15 @@ const char* cpr_status_string(cpr_status s) {
 const char* cpr_last_error(const cpr_ctx* ctx) { return ctx ? ctx->last_error : ""; }
 
 cpr_status cpr_tables(int32_t order_p, double* xi, double* w, double* gLp, double* gRp) {
+  return cpr_scheme_tables(CPR_SCHEME_GL_LP, order_p, xi, w, gLp, gRp);
+}
+
+cpr_status cpr_scheme_tables(int32_t scheme, int32_t order_p, double* xi, double* w, double* gLp,
+                             double* gRp) {
+  if (scheme != CPR_SCHEME_GL_LP && scheme != CPR_SCHEME_GLL_CHAIN) return CPR_EINVAL;
   Tables1D T;
-  if (!build_tables(order_p, &T)) return CPR_EINVAL;
+  if (!build_tables(order_p, scheme == CPR_SCHEME_GLL_CHAIN ? kLobatto : kGauss, &T))
+    return CPR_EINVAL;
   for (int i = 0; i <= order_p; ++i) {
     if (xi) xi[i] = T.xi[i];
     if (w) w[i] = T.w[i];
@@ -173,7 +180,7 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   if (c.precision != CPR_FP64 && c.precision != CPR_FP32_BULK) return CPR_EINVAL;
   if (!(std::isfinite(c.gamma) && c.gamma > 1.0)) return CPR_EINVAL;
   if (c.limiter != CPR_LIM_NONE && c.limiter != CPR_LIM_TVB_CHAR) return CPR_EINVAL;
-  if (c.reserved0 != 0) return CPR_EINVAL;
+  if (c.scheme != CPR_SCHEME_GL_LP && c.scheme != CPR_SCHEME_GLL_CHAIN) return CPR_EINVAL;
   if (!(std::isfinite(c.tvb_m) && c.tvb_m >= 0.0)) return CPR_EINVAL;
   if (!(std::isfinite(c.cfl) && c.cfl >= 0.0)) return CPR_EINVAL;
   if (!std::isfinite(c.t_end)) return CPR_EINVAL;
@@ -183,7 +190,7 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   std::memset(x, 0, sizeof(*x));
   x->cfg = c;
   x->stream = static_cast<hipStream_t>(stream);
-  if (!build_tables(c.order_p, &x->tab)) {
+  if (!build_tables(c.order_p, c.scheme == CPR_SCHEME_GLL_CHAIN ? kLobatto : kGauss, &x->tab)) {
     delete x;
     return CPR_EINVAL;
   }
@@ -305,6 +312,10 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
     set_err(ctx, "cpr_residual_vjp: out must not alias q or v");
     return CPR_EINVAL;
   }
+  if (ctx->cfg.scheme != CPR_SCHEME_GL_LP) {
+    set_err(ctx, "cpr_residual_vjp: only the Gauss-Legendre scheme is differentiated");
+    return CPR_EUNSUPPORTED;
+  }
   return vjp(ctx, q, v, nullptr, nullptr, out, 0.0, 1.0, 0.0, 0.0);
 }
 
@@ -314,6 +325,10 @@ cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt, const do
   if (!(std::isfinite(dt) && dt > 0.0)) return CPR_EINVAL;
   if (ctx->cfg.limiter != CPR_LIM_NONE) {
     set_err(ctx, "cpr_adjoint_step: the limiter is not differentiated");
+    return CPR_EUNSUPPORTED;
+  }
+  if (ctx->cfg.scheme != CPR_SCHEME_GL_LP) {
+    set_err(ctx, "cpr_adjoint_step: only the Gauss-Legendre scheme is differentiated");
     return CPR_EUNSUPPORTED;
   }
   if ((const double*)lam_n == q_n) return CPR_EINVAL;

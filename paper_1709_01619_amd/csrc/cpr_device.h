@@ -15,9 +15,9 @@
 
 namespace cpr {
 
-// Tables for N1 = P+1 points in the compute type R (kernel argument). The
-// Gauss points are symmetric about the element centre, so the tables are
-// too: D[N1-1-i][N1-1-l] = -D[i][l], l_l(+1) = l_{N1-1-l}(-1) and
+// Tables for N1 = P+1 points in the compute type R (kernel argument). Both
+// point sets (Gauss and Gauss-Lobatto) are symmetric about the element
+// centre, so the tables are too: D[N1-1-i][N1-1-l] = -D[i][l], l_l(+1) = l_{N1-1-l}(-1) and
 // gR'(xi_i) = -gL'(xi_{N1-1-i}); the host tables hold these identities
 // exactly. Only the independent half is passed (rows i <= N1/2 of D, with
 // the centre row's own symmetry, l(-1) and gL'), which halves the scalar
@@ -180,6 +180,53 @@ __device__ __forceinline__ void line_ops(const R q[4][N1], const KTab<R, N1>& T,
 #pragma unroll
     for (int i = 0; i < N1; ++i) dF[k][i] = dot_n<N1>([&](int n) { return T.D(i, n); }, F[k]);
   }
+}
+
+// The same line operations for the Gauss-Lobatto scheme with the chain-rule
+// divergence (Section 2.2; the CPR flux kernel, Algorithms 7 and 8). The end
+// points are solution points, so the face states are the end values and the
+// face fluxes the fluxes there; dF at each point is the flux Jacobian applied
+// to the derivative of the solution polynomial, A(q) (D q), formed without
+// the matrix. With u_n = q_n / rho the velocity along the line, u_t across
+// it, and du_n = (dm_n - u_n drho) / rho:
+//   dp              = (g-1) (dE + |V|^2/2 drho - (u_n dm_n + u_t dm_t))
+//   d(m_n)          = dm_n
+//   d(m_n u_n + p)  = dm_n u_n + m_n du_n + dp
+//   d(m_t u_n)      = dm_t u_n + m_t du_n
+//   d(u_n (E + p))  = du_n (E + p) + u_n (dE + dp)
+// Every expression is written in line-normal and line-tangential terms, so
+// the two sweeps round identically on transposed data.
+template <int N1, int AX, typename R>
+__device__ __forceinline__ void line_ops_chain(const R q[4][N1], const KTab<R, N1>& T, R gm1,
+                                               R qlo[4], R qhi[4], R flo[4], R fhi[4],
+                                               R dF[4][N1], bool& bad) {
+  constexpr int NN = 1 + AX, TT = 2 - AX;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    R dq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dq[k] = dot_n<N1>([&](int n) { return T.D(i, n); }, q[k]);
+    const R rho = q[0][i], mn = q[NN][i], mt = q[TT][i], E = q[3][i];
+    const R ir = recip(rho);
+    const R un = mn * ir, ut = mt * ir;
+    const R p = gm1 * r_fma(-(R(0.5) * sym_dot2(q[1][i], q[1][i], q[2][i], q[2][i])), ir, E);
+    bad = bad || nonphysical(rho, p);
+    const R dun = r_fma(-un, dq[0], dq[NN]) * ir;
+    const R dp = gm1 * r_fma(R(0.5) * sym_dot2(un, un, ut, ut), dq[0],
+                             dq[3] - sym_dot2(un, dq[NN], ut, dq[TT]));
+    dF[0][i] = dq[NN];
+    dF[NN][i] = r_fma(mn, dun, r_fma(dq[NN], un, dp));
+    dF[TT][i] = r_fma(mt, dun, dq[TT] * un);
+    dF[3][i] = r_fma(E + p, dun, un * (dq[3] + dp));
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    qlo[k] = q[k][0];
+    qhi[k] = q[k][N1 - 1];
+  }
+  R un, p, ir;
+  euler_flux<AX>(qlo, gm1, flo, un, p, ir);
+  euler_flux<AX>(qhi, gm1, fhi, un, p, ir);
 }
 
 // Coalesced copy between one tile of a state (4 variables x kTile element

@@ -11,9 +11,14 @@ namespace cpr {
 constexpr int kMaxP = 4;
 constexpr int kTile = 8;  // elements per tile edge; one tile per workgroup
 
+// Solution point sets: Gauss-Legendre, or Gauss-Lobatto-Legendre (end
+// points included).
+enum { kGauss = 0, kLobatto = 1 };
+
 // 1D tables on [-1, 1] for degree P, float64 (host).
 struct Tables1D {
   int P;
+  int points;                      // kGauss or kLobatto
   double xi[kMaxP + 1];
   double w[kMaxP + 1];
   double D[kMaxP + 1][kMaxP + 1];  // D[i][l] = l_l'(xi_i)
@@ -23,7 +28,7 @@ struct Tables1D {
   double gRp[kMaxP + 1];           // gR'(xi_i)
 };
 
-bool build_tables(int P, Tables1D* T);
+bool build_tables(int P, int points, Tables1D* T);
 
 struct Geometry {
   int nx, ny;    // elements

@@ -11,6 +11,11 @@
 // with face states extrapolated from each element's polynomial and the
 // Rusanov common flux (Section 4) at every face point.
 //
+// CHAIN selects the paper's own CPR (Gauss-Lobatto points, Section 2.2 and
+// the CPR flux kernel of Algorithms 7 and 8): face states are end values,
+// so a neighbour contributes one point per line, and D f is replaced by the
+// chain rule A(q) (D q) (line_ops_chain).
+//
 // A workgroup holds TPW tiles side by side; the tiles share only the
 // barriers. With P = 4 in float64 a one-tile workgroup has 5 waves and
 // needs more than 128 VGPRs per lane, and a CU then hosts only one such
@@ -45,7 +50,7 @@ struct TilesPerGroup {
   static constexpr int value = (N1 == 5 && sizeof(R) == 8) ? 2 : 1;
 };
 
-template <int P, typename R, int MODE>
+template <int P, typename R, int MODE, bool CHAIN>
 __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) void stage_kernel(
     Geometry G, KTab<R, P + 1> T, StageArgs A) {
   constexpr int N1 = P + 1;
@@ -128,11 +133,19 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       }
       if (hact && hout) {
         const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
+        if (CHAIN) {
+          // the neighbour's end point on the face that touches this tile
+          const int nf = (hs == 0 || hs == 2) ? N1 - 1 : 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+          for (int k = 0; k < 4; ++k)
+            hraw[k][0] = base[k * plane + (hs < 2 ? hm * N1 + nf : nf * N1 + hm)];
+        } else {
 #pragma unroll
-          for (int n = 0; n < N1; ++n)
-            hraw[k][n] = base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int n = 0; n < N1; ++n)
+              hraw[k][n] = base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+        }
       }
     }
 #pragma unroll
@@ -147,7 +160,10 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
         if (ok && f < seg_len) dst[tc.loff[it]] = v[u][it];
       }
     }
-    if (halo && hact && hout) {
+    if (CHAIN && halo && hact && hout) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hq[k] = (R)hraw[k][0];
+    } else if (halo && hact && hout) {
       R ln[4][N1];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -174,16 +190,22 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       off = hm;
       stride = N1;
     }
-    R ln[4][N1];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int n = 0; n < N1; ++n) ln[k][n] = (R)qs[k * VS + e * S + off + n * stride];
     const bool lo = (hs == 0 || hs == 2);
     R qin[4];
+    if (CHAIN) {
+      const int n = lo ? 0 : N1 - 1;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      qin[k] = dot_n<N1>([&](int n) { return lo ? T.em(n) : T.ep(n); }, ln[k]);
+      for (int k = 0; k < 4; ++k) qin[k] = (R)qs[k * VS + e * S + off + n * stride];
+    } else {
+      R ln[4][N1];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int n = 0; n < N1; ++n) ln[k][n] = (R)qs[k * VS + e * S + off + n * stride];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        qin[k] = dot_n<N1>([&](int n) { return lo ? T.em(n) : T.ep(n); }, ln[k]);
+    }
     if (!hout) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) hq[k] = qin[k];
@@ -226,7 +248,10 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   {
     R qlo[4], qhi[4], flo[4], fhi[4], dF[4][N1];
     bool b1 = false, b2 = false;
-    line_ops<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+    if constexpr (CHAIN)
+      line_ops_chain<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+    else
+      line_ops<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     R qnb[4], Fs[4], Fn[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], kTile, 64);
@@ -272,7 +297,10 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       for (int n = 0; n < N1; ++n) qr[k][n] = (R)qrow[k][n];
     R qlo[4], qhi[4], flo[4], fhi[4], dF[4][N1];
     bool b1 = false, b2 = false;
-    line_ops<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+    if constexpr (CHAIN)
+      line_ops_chain<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+    else
+      line_ops<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     R qnb[4], Fw[4], Fe[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], 1, 64);
@@ -380,10 +408,15 @@ static hipError_t launch_stage_t(int mode, const Geometry& g, const Tables1D& T,
   constexpr int TPW = TilesPerGroup<P + 1, R>::value;
   const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T, g);
   const dim3 grid((g.ntx * g.nty + TPW - 1) / TPW), block(64 * (P + 1) * TPW);
-  if (mode == kStageRK)
-    hipLaunchKernelGGL((stage_kernel<P, R, kStageRK>), grid, block, 0, s, g, kt, a);
+  const bool chain = T.points == kLobatto;
+  if (mode == kStageRK && !chain)
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageRK, false>), grid, block, 0, s, g, kt, a);
+  else if (mode == kStageRK)
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageRK, true>), grid, block, 0, s, g, kt, a);
+  else if (!chain)
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageResidual, false>), grid, block, 0, s, g, kt, a);
   else
-    hipLaunchKernelGGL((stage_kernel<P, R, kStageResidual>), grid, block, 0, s, g, kt, a);
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageResidual, true>), grid, block, 0, s, g, kt, a);
   return hipGetLastError();
 }
 

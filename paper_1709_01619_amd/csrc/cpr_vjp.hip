@@ -458,6 +458,7 @@ static hipError_t launch_vjp_t(const Geometry& g, const Tables1D& T, const VjpAr
 
 hipError_t launch_vjp(int P, bool fp32, const Geometry& g, const Tables1D& T, const VjpArgs& a,
                       hipStream_t s) {
+  if (T.points != kGauss) return hipErrorInvalidValue;  // the transpose of the Gauss scheme only
   switch (P) {
     case 1: return fp32 ? launch_vjp_t<1, float>(g, T, a, s) : launch_vjp_t<1, double>(g, T, a, s);
     case 2: return fp32 ? launch_vjp_t<2, float>(g, T, a, s) : launch_vjp_t<2, double>(g, T, a, s);

@@ -17,6 +17,7 @@ from . import _lib
 
 BC = {"periodic": _lib.CPR_BC_PERIODIC, "transmissive": _lib.CPR_BC_TRANSMISSIVE}
 PRECISION = {"fp64": _lib.CPR_FP64, "fp32_bulk": _lib.CPR_FP32_BULK}
+SCHEME = {"gl_lp": _lib.CPR_SCHEME_GL_LP, "gll_chain": _lib.CPR_SCHEME_GLL_CHAIN}
 
 
 def _torch():
@@ -25,13 +26,16 @@ def _torch():
 
 
 class Solver:
-    """One CPR discretisation (degree P, mesh, boundary, precision, limiter)
-    bound to a GPU. States are float64 tensors of shape (4, ny, nx, P+1, P+1)
-    on that GPU (see include/cpr.h for the layout)."""
+    """One CPR discretisation (degree P, mesh, boundary, precision, limiter,
+    scheme) bound to a GPU. States are float64 tensors of shape
+    (4, ny, nx, P+1, P+1) on that GPU (see include/cpr.h for the layout).
+    scheme: "gl_lp" (Gauss-Legendre points, derivative of the flux
+    interpolant) or "gll_chain" (the paper's CPR: Gauss-Lobatto points,
+    chain-rule divergence)."""
 
     def __init__(self, P, nx, ny, x0=0.0, x1=10.0, y0=0.0, y1=10.0, bc="periodic",
                  precision="fp64", gamma=1.4, limiter=False, tvb_m=10.0, cfl=0.0, t_end=0.0,
-                 device="cuda"):
+                 device="cuda", scheme="gl_lp"):
         torch = _torch()
         self.lib = _lib.load()
         self.device = torch.device(device)
@@ -45,10 +49,13 @@ class Solver:
         self.precision = precision
         self.gamma = float(gamma)
         self.limiter = bool(limiter)
+        if scheme not in SCHEME:
+            raise ValueError(f"unknown scheme {scheme}")
+        self.scheme = scheme
         cfg = _lib.make_config(self.P, self.nx, self.ny, self.x0, self.x1, self.y0, self.y1,
                                BC[bc], PRECISION[precision], self.gamma,
                                _lib.CPR_LIM_TVB_CHAR if limiter else _lib.CPR_LIM_NONE,
-                               float(tvb_m), float(cfl), float(t_end))
+                               float(tvb_m), float(cfl), float(t_end), SCHEME[scheme])
         self._ctx = c_void_p()
         with torch.cuda.device(self.device):
             st = self.lib.cpr_init(byref(cfg), c_void_p(self._stream()), byref(self._ctx))
@@ -215,7 +222,7 @@ class Solver:
         """w_i w_j dx dy / 4 per solution point, (n1, n1) float64 tensor,
         from the library's own quadrature table."""
         torch = _torch()
-        _, w, _, _ = _lib.tables(self.P)
+        _, w, _, _ = _lib.tables(self.P, SCHEME[self.scheme])
         w = torch.tensor(w, dtype=torch.float64, device=self.device)
         return torch.outer(w, w) * (self.dx * self.dy / 4.0)
 

@@ -29,7 +29,7 @@ def make_solver(grid, precision="fp64", limiter=False, tvb_m=10.0, cfl=0.0, t_en
     from paper_1709_01619_amd import Solver
     return Solver(grid.P, grid.nx, grid.ny, grid.x0, grid.x1, grid.y0, grid.y1, bc=grid.bc,
                   precision=precision, gamma=grid.gamma, limiter=limiter, tvb_m=tvb_m, cfl=cfl,
-                  t_end=t_end)
+                  t_end=t_end, scheme=grid.scheme)
 
 
 def rel_err(a, b):

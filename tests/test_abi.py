@@ -54,7 +54,7 @@ def test_config_struct_layout_matches_header():
 @pytest.mark.parametrize("field,value", [
     ("abi_version", 99), ("order_p", 0), ("order_p", 5), ("nx", 0), ("ny", -3),
     ("x1", 0.0), ("y1", -1.0), ("bc", 7), ("precision", 3), ("gamma", 1.0),
-    ("gamma", float("nan")), ("limiter", 2), ("reserved0", 1), ("tvb_m", -1.0), ("cfl", -0.1),
+    ("gamma", float("nan")), ("limiter", 2), ("scheme", 2), ("tvb_m", -1.0), ("cfl", -0.1),
     ("t_end", float("inf")), ("nx", (1 << 20) + 1),
 ])
 def test_init_rejects_invalid_config_without_gpu(field, value):
@@ -103,3 +103,22 @@ def test_library_tables_agree_with_oracle(P):
     np.testing.assert_allclose(gl, T.gLp, atol=1e-13)
     np.testing.assert_allclose(gr, T.gRp, atol=1e-13)
     assert lib.cpr_tables(0, None, None, None, None) == L.CPR_EINVAL
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_library_lobatto_tables_agree_with_oracle(P):
+    """cpr_scheme_tables for the Gauss-Lobatto scheme: Newton iteration on
+    L_P' and the Legendre derivative recurrence in the library, numpy's
+    Legendre-series roots and derivatives in the oracle."""
+    L, lib = _lib()
+    from oracle import tables
+    xi, w, gl, gr = L.tables(P, L.CPR_SCHEME_GLL_CHAIN)
+    T = tables.get(P, "gll")
+    np.testing.assert_allclose(xi, T.xi, atol=2e-16)
+    np.testing.assert_allclose(w, T.w, atol=1e-15)
+    np.testing.assert_allclose(gl, T.gLp, atol=1e-13)
+    np.testing.assert_allclose(gr, T.gRp, atol=1e-13)
+    # the default scheme's tables are cpr_tables' own
+    assert L.tables(P, L.CPR_SCHEME_GL_LP) == L.tables(P)
+    assert lib.cpr_scheme_tables(2, P, None, None, None, None) == L.CPR_EINVAL
+    assert lib.cpr_scheme_tables(L.CPR_SCHEME_GLL_CHAIN, 5, None, None, None, None) == L.CPR_EINVAL
