@@ -17,7 +17,12 @@ Printed: one JSON line (rank 0). Extra objects:
   roofline      the stage kernel against HBM bandwidth (algorithmic bytes:
                 64 B per unknown per step = 21.33 B per unknown per launch)
   cpu_baseline  the CPU oracle timed on a bounded sample of the workload
-  fp32_bulk, l2_error, adjoint, scale_p4_1024: see the keys.
+  fp32_bulk, l2_error, adjoint, scale_p4_1024, c1_small, c3_limited_riemann,
+  c5_adjoint: see the keys.
+  paper_cpr_gll_chain  the paper's own CPR scheme (Gauss-Lobatto points,
+                chain-rule divergence): stage timings, and the paper's
+                smooth-problem errors (Tables 2 and 3) reproduced by both
+                schemes.
 """
 
 from __future__ import annotations
@@ -252,6 +257,67 @@ def adjoint_p4():
     return out
 
 
+def paper_scheme():
+    """The paper's own CPR (Gauss-Lobatto points, chain-rule divergence):
+    its stage kernel on the headline workload (P=3 256^2, FP64 and
+    FP32-bulk) and on P=4 1024^2, and the paper's smooth-problem protocol
+    (vortex of strength 5, mean flow (1,1,0,1), periodic [-5,5]^2, CFL of
+    Table 1, device CFL steps to t=1) for both schemes against the errors
+    of Tables 2 and 3 (CPR column for the chain rule, DG column for the
+    Gauss-Legendre scheme)."""
+    import torch
+    import inputs
+    from paper_1709_01619_amd import Solver
+    from tests.golden_data import paper_vortex_l2
+    out = {"scheme": "gll_chain"}
+    for P, n, steps, prec in ((3, 256, 300, "fp64"), (3, 256, 300, "fp32_bulk"),
+                              (4, 1024, 20, "fp64")):
+        s = Solver(P, n, n, precision=prec, scheme="gll_chain")
+        q = vortex_state(s)
+        dt = 1e-4 if n == 1024 else c2_dt(s, q)[0]
+        ms = time_steps(s, q, dt, steps, 5)
+        s.sync()
+        U = s.n_unknowns
+        ach = BYTES_PER_UNKNOWN_STEP / 3.0 * U / (ms * 1e-3 / 3.0) / 1e9
+        out[f"p{P}_{n}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": 3.0 * U / (ms * 1e-3),
+                                   "hbm_frac": round(ach / HBM_PEAK_GBS, 4)}
+        log("chain", P, n, prec, out[f"p{P}_{n}_{prec}"])
+        del s, q
+    V = inputs.Vortex(eps=5.0, lo=-5.0, hi=5.0, u_inf=1.0, v_inf=0.0, center=(0.0, 0.0))
+    rows = []
+    for scheme, col in (("gll_chain", 3), ("gl_lp", 4)):
+        prev = None
+        for r in paper_vortex_l2():
+            P, n, cfl = r[0], r[1], r[2]
+            s = Solver(P, n, n, -5.0, 5.0, -5.0, 5.0, cfl=cfl, t_end=1.0, scheme=scheme)
+            x, y = s.coords()
+            xn, yn = x.cpu().numpy(), y.cpu().numpy()
+            q = torch.from_numpy(V.conserved(xn, yn)).cuda()
+            ex = torch.from_numpy(V.conserved(xn, yn, 1.0)).cuda()
+            lam = s.max_wavespeed(q)
+            nmax = int(math.ceil(1.0 / (cfl * s.dx / (1.25 * lam)))) + 2
+            s.set_time(0.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(nmax):
+                s.step(q, 0.0)
+            t, _ = s.get_time()
+            el = time.perf_counter() - t0
+            e = s.l2_diff(q, ex, 0)
+            slope = None
+            if prev is not None and prev[0] == P:
+                slope = math.log(prev[2] / e) / math.log(n / prev[1])
+            prev = (P, n, e)
+            rows.append({"scheme": scheme, "P": P, "mesh": n, "cfl": cfl, "t": t,
+                         "l2_rho": e, "paper": r[col], "ratio_to_paper": e / r[col],
+                         "slope": slope, "s_to_solution": el})
+            del s, q, ex
+    out["paper_smooth_problem"] = rows
+    out["max_abs_log_ratio_to_paper"] = max(abs(math.log(r["ratio_to_paper"])) for r in rows)
+    log("paper smooth problem", json.dumps(rows))
+    return out
+
+
 def profile_legs(a):
     """Run selected legs only (used under rocprofv3): no JSON line."""
     import torch
@@ -273,6 +339,12 @@ def profile_legs(a):
             dt, _ = c2_dt(s, q)
             ms = time_steps(s, q, dt, a.steps, a.warmup)
             print(f"main P=3 256^2 {prec}: {ms:.4f} ms/step", flush=True)
+    if "chain" in legs:
+        for P, n, prec in ((3, 256, "fp64"), (3, 256, "fp32_bulk"), (4, 1024, "fp64")):
+            s = Solver(P, n, n, precision=prec, scheme="gll_chain")
+            q = vortex_state(s)
+            ms = time_steps(s, q, 1e-4, a.steps, a.warmup)
+            print(f"chain P={P} {n}^2 {prec}: {ms:.4f} ms/step", flush=True)
     if "scale" in legs:
         for prec in ("fp64", "fp32_bulk"):
             s = Solver(4, 1024, 1024, precision=prec)
@@ -291,7 +363,7 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true",
                     help="skip the t=10 error runs, the adjoint and the P=4 legs")
     ap.add_argument("--legs", default="all",
-                    help="comma list of legs to run for profiling: main, l2, adjoint, scale, "
+                    help="comma list of legs to run for profiling: main, scale, chain, "
                          "copy (a 1 GiB device copy that calibrates HBM byte counters); "
                          "prints a short text report instead of the JSON line")
     a = ap.parse_args(argv)
@@ -418,6 +490,7 @@ def main(argv=None):
         extra["c3_limited_riemann"] = limited_riemann()
         log("c3", extra["c3_limited_riemann"])
         extra["c5_adjoint"] = adjoint_p4()
+        extra["paper_cpr_gll_chain"] = paper_scheme()
     copy_gbs = copy_bandwidth()
     roofline["copy_gbs"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
