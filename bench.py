@@ -402,7 +402,7 @@ def main(argv=None):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "cpr::stage_kernel<3,double,0>",
+                "kernel": "cpr::stage_kernel<3,double,0,false>",
                 "note": "256^2 P=3 states are 33.6 MB each, so the three live states fit the "
                         "256 MB Infinity Cache; see scale_p4_1024 for an HBM-resident case"}
 
