@@ -22,10 +22,17 @@ inside extrapolated state, so the face flux is F(q_inside)).
 Scheme "gll_chain" is the paper's own CPR (Section 2.2 with Gauss-Lobatto
 solution points; the chain-rule divergence of its CPR flux kernel,
 Algorithms 7 and 8): the face states and face fluxes are the end values of
-each line, and Pi[div F] is the chain rule A(q) dq/dx + B(q) dq/dy at every solution point, with dq/dx the
-derivative of the solution polynomial. The correction term is unchanged. The
-chain rule does not telescope, so this scheme is not discretely
-conservative for the nonlinear fluxes.
+each line, and Pi[div F] is the chain rule A(q) dq/dx + B(q) dq/dy at every
+solution point, with dq/dx the derivative of the solution polynomial. The
+correction term is unchanged. The chain rule does not telescope, so this
+scheme is not discretely conservative for the nonlinear fluxes.
+
+Scheme "gll_lp" is the paper's nodal DG (NDG, Section 2.4: the strong form
+with the flux derivative D f and the lift of the face-flux jumps, M^-1 E)
+written in the same differential form: Gauss-Lobatto points, the derivative
+of the flux interpolant, and the Radau correction, whose derivatives at the
+nodes are the lift columns of the exact mass matrix. The same residual as
+the default scheme on Lobatto points; discretely conservative.
 """
 
 from __future__ import annotations
@@ -40,6 +47,8 @@ PERIODIC = "periodic"
 TRANSMISSIVE = "transmissive"
 GL_LP = "gl_lp"          # Gauss-Legendre points, derivative of the flux interpolant
 GLL_CHAIN = "gll_chain"  # Gauss-Lobatto points, chain-rule divergence (the paper's CPR)
+GLL_LP = "gll_lp"        # Gauss-Lobatto points, derivative of the flux interpolant (NDG)
+SCHEMES = (GL_LP, GLL_CHAIN, GLL_LP)
 
 
 @dataclass(frozen=True)
@@ -66,7 +75,7 @@ class Grid:
             raise ValueError(f"unknown boundary condition {self.bc}")
         if not self.gamma > 1.0:
             raise ValueError("gamma must exceed 1")
-        if self.scheme not in (GL_LP, GLL_CHAIN):
+        if self.scheme not in SCHEMES:
             raise ValueError(f"unknown scheme {self.scheme}")
 
     @property
@@ -90,7 +99,7 @@ class Grid:
         return 4 * self.ny * self.nx * self.n1 * self.n1
 
     def tables(self):
-        return tables.get(self.P, "gll" if self.scheme == GLL_CHAIN else "gl")
+        return tables.get(self.P, "gl" if self.scheme == GL_LP else "gll")
 
     def coords(self):
         """Physical coordinates (x, y), each of shape (ny, nx, n1, n1), of the

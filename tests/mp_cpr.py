@@ -3,10 +3,11 @@ the definitions (no tables): Gauss-Legendre nodes as roots of L_{P+1} (or
 Gauss-Lobatto nodes: -1, +1 and the roots of L_P') found by mpmath, Lagrange
 polynomials as products, Radau correction polynomials from mpmath's Legendre
 functions, and derivatives by mpmath's numerical differentiation: of the
-corrected flux polynomial (scheme gl_lp), or, for the chain rule (scheme
-gll_chain), of the solution polynomial, pushed through the flux as a
-directional derivative d/ds F(q + s dq) at s = 0. Used only to pin the
-oracle on tiny meshes; it shares nothing with the oracle."""
+corrected flux polynomial (schemes gl_lp on Gauss points and gll_lp on
+Lobatto points), or, for the chain rule (scheme gll_chain), of the solution
+polynomial, pushed through the flux as a directional derivative
+d/ds F(q + s dq) at s = 0. Used only to pin the oracle on tiny meshes; it
+shares nothing with the oracle."""
 
 import mpmath as mp
 
@@ -68,7 +69,7 @@ def residual(q, P, nx, ny, x0, x1, y0, y1, bc, gamma, dps=50, scheme="gl_lp"):
     mp.mp.dps = dps
     g = mp.mpf(gamma)
     n1 = P + 1
-    nodes = gll_nodes(n1) if scheme == "gll_chain" else gl_nodes(n1)
+    nodes = gl_nodes(n1) if scheme == "gl_lp" else gll_nodes(n1)
     dx = (mp.mpf(x1) - mp.mpf(x0)) / nx
     dy = (mp.mpf(y1) - mp.mpf(y0)) / ny
 

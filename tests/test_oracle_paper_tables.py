@@ -1,7 +1,8 @@
 """The oracle against the errors the paper prints for its smooth problem
 (Section 4, "Smooth Problem"; Tables 2 and 3, CFL from Table 1): the
-Gauss-Lobatto chain-rule scheme reproduces the CPR column and the
-Gauss-Legendre scheme the DG column. Each run takes CFL-limited steps,
+Gauss-Lobatto chain-rule scheme reproduces the CPR column, the
+Gauss-Legendre scheme the DG column and the Gauss-Lobatto scheme with the
+flux derivative the NDG column. Each run takes CFL-limited steps,
 dt = CFL h / max(|V| + c) from the current state, with the last step cut to
 end at t = 1, then the area-normalised quadrature L2 norm of the density
 error (the meshes up to 40x40 here; the HIP path runs all of them)."""
@@ -10,7 +11,7 @@ import pytest
 
 import inputs
 from oracle import cpr
-from tests.golden_data import PAPER_L2_RTOL, paper_vortex_l2
+from tests.golden_data import PAPER_COLUMN, PAPER_L2_RTOL, paper_vortex_l2
 
 
 def paper_vortex():
@@ -32,10 +33,11 @@ def run_to_one(grid, cfl):
 ROWS = [r for r in paper_vortex_l2() if r[1] <= 40]
 
 
-@pytest.mark.parametrize("P,n,cfl,cpr_err,dg_err", ROWS)
-@pytest.mark.parametrize("scheme", [cpr.GLL_CHAIN, cpr.GL_LP])
-def test_oracle_reproduces_paper_errors(scheme, P, n, cfl, cpr_err, dg_err):
+@pytest.mark.parametrize("row", ROWS, ids=lambda r: f"P{r[0]}-{r[1]}")
+@pytest.mark.parametrize("scheme", cpr.SCHEMES)
+def test_oracle_reproduces_paper_errors(scheme, row):
+    P, n, cfl = row[:3]
     g = cpr.Grid(P=P, nx=n, ny=n, x0=-5.0, x1=5.0, y0=-5.0, y1=5.0, scheme=scheme)
-    want = cpr_err if scheme == cpr.GLL_CHAIN else dg_err
+    want = row[PAPER_COLUMN[scheme]]
     got = run_to_one(g, cfl)
     assert abs(got - want) <= PAPER_L2_RTOL * want, (got, want)
