@@ -24,6 +24,13 @@
  * lift. The chain rule does not telescope, so this scheme conserves mass
  * exactly but momentum and energy only to truncation error.
  *
+ * Scheme CPR_SCHEME_GLL_LP is the paper's nodal DG (Section 2.4: D f plus
+ * the lift M^-1 M^A of the face-flux jumps, on Gauss-Lobatto points), which
+ * is the differential form above with the derivative of the flux
+ * interpolant on the Gauss-Lobatto points: the Radau derivatives at those
+ * nodes are the lift columns of the exact mass matrix. Exactly
+ * conservative.
+ *
  * State layout (every q, r, v, lambda buffer): contiguous float64 (float32
  * for the FP32-bulk residual output) array q[k][J][I][j][i] of
  * 4 * ny * nx * (P+1)^2 values, C order:
@@ -33,7 +40,7 @@
  * Solution point (I,J,i,j) sits at x = x0 + (I + 1/2 + xi_i/2) dx,
  * y = y0 + (J + 1/2 + xi_j/2) dy with xi the ascending nodes of the
  * context's point set (Gauss-Legendre, or Gauss-Lobatto for
- * CPR_SCHEME_GLL_CHAIN).
+ * CPR_SCHEME_GLL_CHAIN and CPR_SCHEME_GLL_LP).
  *
  * Ownership: all array arguments are device pointers owned by the caller
  * (unless documented as host pointers). The library owns its scratch,
@@ -74,7 +81,7 @@ typedef enum {
 enum { CPR_BC_PERIODIC = 0, CPR_BC_TRANSMISSIVE = 1 };
 enum { CPR_FP64 = 0, CPR_FP32_BULK = 1 };
 enum { CPR_LIM_NONE = 0, CPR_LIM_TVB_CHAR = 1 };
-enum { CPR_SCHEME_GL_LP = 0, CPR_SCHEME_GLL_CHAIN = 1 };
+enum { CPR_SCHEME_GL_LP = 0, CPR_SCHEME_GLL_CHAIN = 1, CPR_SCHEME_GLL_LP = 2 };
 
 typedef struct {
   int32_t abi_version;  /* must equal CPR_ABI_VERSION                     */
@@ -89,7 +96,8 @@ typedef struct {
                            sums and norms in float64                     */
   double gamma;         /* ratio of specific heats, > 1                   */
   int32_t limiter;      /* CPR_LIM_NONE or CPR_LIM_TVB_CHAR               */
-  int32_t scheme;       /* CPR_SCHEME_GL_LP or CPR_SCHEME_GLL_CHAIN       */
+  int32_t scheme;       /* CPR_SCHEME_GL_LP, CPR_SCHEME_GLL_CHAIN or
+                           CPR_SCHEME_GLL_LP                              */
   double tvb_m;         /* TVB constant M >= 0 (limiter only)             */
   double cfl;           /* CFL number for device-computed dt, > 0         */
   double t_end;         /* final time for device-computed dt (clips the
@@ -186,9 +194,10 @@ cpr_status cpr_point_coords(cpr_ctx* ctx, double* x, double* y);
 cpr_status cpr_tables(int32_t order_p, double* xi, double* w, double* gLp, double* gRp);
 
 /* The same tables for a scheme's point set: CPR_SCHEME_GL_LP as
- * cpr_tables; CPR_SCHEME_GLL_CHAIN the Gauss-Lobatto-Legendre nodes (-1, the
- * roots of L_P', +1), weights 2 / (P (P+1) L_P(xi)^2), and the Radau
- * correction derivatives at those nodes (Section 2.2). No context or device
+ * cpr_tables; CPR_SCHEME_GLL_CHAIN and CPR_SCHEME_GLL_LP the
+ * Gauss-Lobatto-Legendre nodes (-1, the roots of L_P', +1), weights
+ * 2 / (P (P+1) L_P(xi)^2), and the Radau correction derivatives at those
+ * nodes (Section 2.2). No context or device
  * needed. CPR_EINVAL for an unknown scheme or P outside 1..4. */
 cpr_status cpr_scheme_tables(int32_t scheme, int32_t order_p, double* xi, double* w, double* gLp,
                              double* gRp);

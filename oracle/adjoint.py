@@ -68,7 +68,12 @@ def rusanov_vjp(qL, qR, s, gamma, axis):
 
 
 def residual_vjp(q, v, grid: Grid):
-    """(dR/dq)^T v for R = oracle.cpr.residual; same shape as q."""
+    """(dR/dq)^T v for R = oracle.cpr.residual; same shape as q. Schemes
+    with the derivative of the flux interpolant only (Gauss-Legendre and
+    Gauss-Lobatto points): the chain rule's transpose would need the second
+    derivatives of the flux."""
+    if grid.scheme == cpr.GLL_CHAIN:
+        raise NotImplementedError("the chain-rule scheme has no transpose here")
     T = grid.tables()
     g = grid.gamma
     out = np.zeros_like(q)

@@ -19,7 +19,7 @@ CPR_OK, CPR_EINVAL, CPR_ENOMEM, CPR_EHIP, CPR_EUNSUPPORTED, CPR_ENONPHYSICAL = 0
 CPR_BC_PERIODIC, CPR_BC_TRANSMISSIVE = 0, 1
 CPR_FP64, CPR_FP32_BULK = 0, 1
 CPR_LIM_NONE, CPR_LIM_TVB_CHAR = 0, 1
-CPR_SCHEME_GL_LP, CPR_SCHEME_GLL_CHAIN = 0, 1
+CPR_SCHEME_GL_LP, CPR_SCHEME_GLL_CHAIN, CPR_SCHEME_GLL_LP = 0, 1, 2
 
 # exported symbols declared in include/cpr.h
 SYMBOLS = (

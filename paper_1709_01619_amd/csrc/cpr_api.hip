@@ -11,6 +11,10 @@
 
 using namespace cpr;
 
+static_assert(CPR_SCHEME_GL_LP == kSchemeGlLp && CPR_SCHEME_GLL_CHAIN == kSchemeGllChain &&
+                  CPR_SCHEME_GLL_LP == kSchemeGllLp,
+              "public and internal scheme values differ");
+
 struct cpr_ctx {
   cpr_config cfg;
   Geometry geo;
@@ -91,8 +95,8 @@ cpr_status stage(cpr_ctx* c, int mode, const double* src, const double* qn, doub
   s.dt_dev = device_dt ? c->dscal + 1 : nullptr;
   s.skip = device_dt ? c->iscr + 1 : nullptr;
   s.err = c->iscr;
-  HIP_TRY(c, launch_stage(c->cfg.order_p, c->cfg.precision == CPR_FP32_BULK, mode, c->geo, c->tab,
-                          s, c->stream),
+  HIP_TRY(c, launch_stage(c->cfg.order_p, c->cfg.precision == CPR_FP32_BULK, c->cfg.scheme, mode,
+                          c->geo, c->tab, s, c->stream),
           "stage kernel launch");
   return CPR_OK;
 }
@@ -124,7 +128,9 @@ cpr_status vjp(cpr_ctx* c, const double* q, const double* v, const double* x, co
   a.beta = beta;
   a.gam = gam;
   a.err = c->iscr;
-  HIP_TRY(c, launch_vjp(c->cfg.order_p, c->cfg.precision == CPR_FP32_BULK, c->geo, c->tab, a, c->stream), "adjoint kernel launch");
+  HIP_TRY(c, launch_vjp(c->cfg.order_p, c->cfg.precision == CPR_FP32_BULK, c->cfg.scheme, c->geo,
+                        c->tab, a, c->stream),
+          "adjoint kernel launch");
   return CPR_OK;
 }
 
@@ -152,10 +158,10 @@ cpr_status cpr_tables(int32_t order_p, double* xi, double* w, double* gLp, doubl
 
 cpr_status cpr_scheme_tables(int32_t scheme, int32_t order_p, double* xi, double* w, double* gLp,
                              double* gRp) {
-  if (scheme != CPR_SCHEME_GL_LP && scheme != CPR_SCHEME_GLL_CHAIN) return CPR_EINVAL;
-  Tables1D T;
-  if (!build_tables(order_p, scheme == CPR_SCHEME_GLL_CHAIN ? kLobatto : kGauss, &T))
+  if (scheme != CPR_SCHEME_GL_LP && scheme != CPR_SCHEME_GLL_CHAIN && scheme != CPR_SCHEME_GLL_LP)
     return CPR_EINVAL;
+  Tables1D T;
+  if (!build_tables(order_p, scheme_points(scheme), &T)) return CPR_EINVAL;
   for (int i = 0; i <= order_p; ++i) {
     if (xi) xi[i] = T.xi[i];
     if (w) w[i] = T.w[i];
@@ -180,7 +186,9 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   if (c.precision != CPR_FP64 && c.precision != CPR_FP32_BULK) return CPR_EINVAL;
   if (!(std::isfinite(c.gamma) && c.gamma > 1.0)) return CPR_EINVAL;
   if (c.limiter != CPR_LIM_NONE && c.limiter != CPR_LIM_TVB_CHAR) return CPR_EINVAL;
-  if (c.scheme != CPR_SCHEME_GL_LP && c.scheme != CPR_SCHEME_GLL_CHAIN) return CPR_EINVAL;
+  if (c.scheme != CPR_SCHEME_GL_LP && c.scheme != CPR_SCHEME_GLL_CHAIN &&
+      c.scheme != CPR_SCHEME_GLL_LP)
+    return CPR_EINVAL;
   if (!(std::isfinite(c.tvb_m) && c.tvb_m >= 0.0)) return CPR_EINVAL;
   if (!(std::isfinite(c.cfl) && c.cfl >= 0.0)) return CPR_EINVAL;
   if (!std::isfinite(c.t_end)) return CPR_EINVAL;
@@ -190,7 +198,7 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   std::memset(x, 0, sizeof(*x));
   x->cfg = c;
   x->stream = static_cast<hipStream_t>(stream);
-  if (!build_tables(c.order_p, c.scheme == CPR_SCHEME_GLL_CHAIN ? kLobatto : kGauss, &x->tab)) {
+  if (!build_tables(c.order_p, scheme_points(c.scheme), &x->tab)) {
     delete x;
     return CPR_EINVAL;
   }
@@ -312,8 +320,8 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
     set_err(ctx, "cpr_residual_vjp: out must not alias q or v");
     return CPR_EINVAL;
   }
-  if (ctx->cfg.scheme != CPR_SCHEME_GL_LP) {
-    set_err(ctx, "cpr_residual_vjp: only the Gauss-Legendre scheme is differentiated");
+  if (ctx->cfg.scheme == CPR_SCHEME_GLL_CHAIN) {
+    set_err(ctx, "cpr_residual_vjp: the chain-rule scheme is not differentiated");
     return CPR_EUNSUPPORTED;
   }
   return vjp(ctx, q, v, nullptr, nullptr, out, 0.0, 1.0, 0.0, 0.0);
@@ -327,8 +335,8 @@ cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt, const do
     set_err(ctx, "cpr_adjoint_step: the limiter is not differentiated");
     return CPR_EUNSUPPORTED;
   }
-  if (ctx->cfg.scheme != CPR_SCHEME_GL_LP) {
-    set_err(ctx, "cpr_adjoint_step: only the Gauss-Legendre scheme is differentiated");
+  if (ctx->cfg.scheme == CPR_SCHEME_GLL_CHAIN) {
+    set_err(ctx, "cpr_adjoint_step: the chain-rule scheme is not differentiated");
     return CPR_EUNSUPPORTED;
   }
   if ((const double*)lam_n == q_n) return CPR_EINVAL;

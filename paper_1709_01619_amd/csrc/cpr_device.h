@@ -156,8 +156,10 @@ __device__ __forceinline__ void rusanov(const R qL[4], const R qR[4], R gam, R g
 
 // Line operations on the N1 points of one element row (AX=0) or column
 // (AX=1): face states qlo (at -1) and qhi (at +1), the flux interpolant's
-// face values flo, fhi, and its derivative dF at the points.
-template <int N1, int AX, typename R>
+// face values flo, fhi, and its derivative dF at the points. On Gauss points
+// (LOB false) the face values are extrapolated; on Gauss-Lobatto points the
+// end points are solution points and the face values are the end values.
+template <int N1, int AX, bool LOB, typename R>
 __device__ __forceinline__ void line_ops(const R q[4][N1], const KTab<R, N1>& T, R gm1,
                                          R qlo[4], R qhi[4], R flo[4], R fhi[4],
                                          R dF[4][N1], bool& bad) {
@@ -173,10 +175,17 @@ __device__ __forceinline__ void line_ops(const R q[4][N1], const KTab<R, N1>& T,
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    qlo[k] = dot_n<N1>([&](int n) { return T.em(n); }, q[k]);
-    qhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, q[k]);
-    flo[k] = dot_n<N1>([&](int n) { return T.em(n); }, F[k]);
-    fhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, F[k]);
+    if (LOB) {
+      qlo[k] = q[k][0];
+      qhi[k] = q[k][N1 - 1];
+      flo[k] = F[k][0];
+      fhi[k] = F[k][N1 - 1];
+    } else {
+      qlo[k] = dot_n<N1>([&](int n) { return T.em(n); }, q[k]);
+      qhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, q[k]);
+      flo[k] = dot_n<N1>([&](int n) { return T.em(n); }, F[k]);
+      fhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, F[k]);
+    }
 #pragma unroll
     for (int i = 0; i < N1; ++i) dF[k][i] = dot_n<N1>([&](int n) { return T.D(i, n); }, F[k]);
   }

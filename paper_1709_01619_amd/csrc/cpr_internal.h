@@ -15,6 +15,13 @@ constexpr int kTile = 8;  // elements per tile edge; one tile per workgroup
 // points included).
 enum { kGauss = 0, kLobatto = 1 };
 
+// Discretisations (the values of cpr_config.scheme): Gauss-Legendre points
+// with the derivative of the flux interpolant; Gauss-Lobatto points with the
+// chain-rule divergence (the paper's CPR); Gauss-Lobatto points with the
+// derivative of the flux interpolant (the paper's NDG).
+enum { kSchemeGlLp = 0, kSchemeGllChain = 1, kSchemeGllLp = 2 };
+inline int scheme_points(int scheme) { return scheme == kSchemeGlLp ? kGauss : kLobatto; }
+
 // 1D tables on [-1, 1] for degree P, float64 (host).
 struct Tables1D {
   int P;
@@ -54,8 +61,8 @@ struct StageArgs {
 
 enum { kStageRK = 0, kStageResidual = 1 };
 
-hipError_t launch_stage(int P, bool fp32, int mode, const Geometry& g, const Tables1D& T,
-                        const StageArgs& a, hipStream_t s);
+hipError_t launch_stage(int P, bool fp32, int scheme, int mode, const Geometry& g,
+                        const Tables1D& T, const StageArgs& a, hipStream_t s);
 
 // out = alpha v + delta J(q)^T v + beta x + gam y   (x, y nullable), with
 // J = dR/dq the Jacobian of the float64 residual.
@@ -68,8 +75,8 @@ struct VjpArgs {
   double alpha, delta, beta, gam;
   int* err;
 };
-hipError_t launch_vjp(int P, bool fp32, const Geometry& g, const Tables1D& T, const VjpArgs& a,
-                      hipStream_t s);
+hipError_t launch_vjp(int P, bool fp32, int scheme, const Geometry& g, const Tables1D& T,
+                      const VjpArgs& a, hipStream_t s);
 
 // Limiter: element means then detect + limit in place.
 struct LimitArgs {

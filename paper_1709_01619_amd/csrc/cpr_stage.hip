@@ -11,10 +11,11 @@
 // with face states extrapolated from each element's polynomial and the
 // Rusanov common flux (Section 4) at every face point.
 //
-// CHAIN selects the paper's own CPR (Gauss-Lobatto points, Section 2.2 and
-// the CPR flux kernel of Algorithms 7 and 8): face states are end values,
-// so a neighbour contributes one point per line, and D f is replaced by the
-// chain rule A(q) (D q) (line_ops_chain).
+// SCH selects the discretisation. On Gauss-Lobatto points (the paper's CPR,
+// Section 2.2 and the CPR flux kernel of Algorithms 7 and 8, and its NDG,
+// Section 2.4) face states are end values, so a neighbour contributes one
+// point per line; the paper's CPR also replaces D f by the chain rule
+// A(q) (D q) (line_ops_chain).
 //
 // A workgroup holds TPW tiles side by side; the tiles share only the
 // barriers. With P = 4 in float64 a one-tile workgroup has 5 waves and
@@ -50,12 +51,14 @@ struct TilesPerGroup {
   static constexpr int value = (N1 == 5 && sizeof(R) == 8) ? 2 : 1;
 };
 
-template <int P, typename R, int MODE, bool CHAIN>
+template <int P, typename R, int MODE, int SCH>
 __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) void stage_kernel(
     Geometry G, KTab<R, P + 1> T, StageArgs A) {
   constexpr int N1 = P + 1;
   constexpr int NSP = N1 * N1;
   constexpr int TPW = TilesPerGroup<N1, R>::value;
+  constexpr bool LOB = SCH != kSchemeGlLp;      // Gauss-Lobatto points
+  constexpr bool CHAIN = SCH == kSchemeGllChain;
   constexpr int NT = 64 * N1;                   // lanes per tile
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;  // odd LDS stride per element
   constexpr int VS = 64 * S;                    // LDS stride per variable
@@ -133,7 +136,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       }
       if (hact && hout) {
         const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
-        if (CHAIN) {
+        if (LOB) {
           // the neighbour's end point on the face that touches this tile
           const int nf = (hs == 0 || hs == 2) ? N1 - 1 : 0;
 #pragma unroll
@@ -160,7 +163,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
         if (ok && f < seg_len) dst[tc.loff[it]] = v[u][it];
       }
     }
-    if (CHAIN && halo && hact && hout) {
+    if (LOB && halo && hact && hout) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) hq[k] = (R)hraw[k][0];
     } else if (halo && hact && hout) {
@@ -192,7 +195,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
     }
     const bool lo = (hs == 0 || hs == 2);
     R qin[4];
-    if (CHAIN) {
+    if (LOB) {
       const int n = lo ? 0 : N1 - 1;
 #pragma unroll
       for (int k = 0; k < 4; ++k) qin[k] = (R)qs[k * VS + e * S + off + n * stride];
@@ -251,7 +254,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
     if constexpr (CHAIN)
       line_ops_chain<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     else
-      line_ops<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+      line_ops<N1, 1, LOB>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     R qnb[4], Fs[4], Fn[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], kTile, 64);
@@ -300,7 +303,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
     if constexpr (CHAIN)
       line_ops_chain<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     else
-      line_ops<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+      line_ops<N1, 0, LOB>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     R qnb[4], Fw[4], Fe[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], 1, 64);
@@ -402,31 +405,38 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   if (bad) atomicOr(A.err, 1);
 }
 
-template <int P, typename R>
-static hipError_t launch_stage_t(int mode, const Geometry& g, const Tables1D& T,
+template <int P, typename R, int SCH>
+static hipError_t launch_stage_s(int mode, const Geometry& g, const KTab<R, P + 1>& kt,
                                  const StageArgs& a, hipStream_t s) {
   constexpr int TPW = TilesPerGroup<P + 1, R>::value;
-  const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T, g);
   const dim3 grid((g.ntx * g.nty + TPW - 1) / TPW), block(64 * (P + 1) * TPW);
-  const bool chain = T.points == kLobatto;
-  if (mode == kStageRK && !chain)
-    hipLaunchKernelGGL((stage_kernel<P, R, kStageRK, false>), grid, block, 0, s, g, kt, a);
-  else if (mode == kStageRK)
-    hipLaunchKernelGGL((stage_kernel<P, R, kStageRK, true>), grid, block, 0, s, g, kt, a);
-  else if (!chain)
-    hipLaunchKernelGGL((stage_kernel<P, R, kStageResidual, false>), grid, block, 0, s, g, kt, a);
+  if (mode == kStageRK)
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageRK, SCH>), grid, block, 0, s, g, kt, a);
   else
-    hipLaunchKernelGGL((stage_kernel<P, R, kStageResidual, true>), grid, block, 0, s, g, kt, a);
+    hipLaunchKernelGGL((stage_kernel<P, R, kStageResidual, SCH>), grid, block, 0, s, g, kt, a);
   return hipGetLastError();
 }
 
-hipError_t launch_stage(int P, bool fp32, int mode, const Geometry& g, const Tables1D& T,
-                        const StageArgs& a, hipStream_t s) {
+template <int P, typename R>
+static hipError_t launch_stage_t(int scheme, int mode, const Geometry& g, const Tables1D& T,
+                                 const StageArgs& a, hipStream_t s) {
+  if (T.points != scheme_points(scheme)) return hipErrorInvalidValue;
+  const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T, g);
+  switch (scheme) {
+    case kSchemeGlLp: return launch_stage_s<P, R, kSchemeGlLp>(mode, g, kt, a, s);
+    case kSchemeGllChain: return launch_stage_s<P, R, kSchemeGllChain>(mode, g, kt, a, s);
+    case kSchemeGllLp: return launch_stage_s<P, R, kSchemeGllLp>(mode, g, kt, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_stage(int P, bool fp32, int scheme, int mode, const Geometry& g,
+                        const Tables1D& T, const StageArgs& a, hipStream_t s) {
   switch (P) {
-    case 1: return fp32 ? launch_stage_t<1, float>(mode, g, T, a, s) : launch_stage_t<1, double>(mode, g, T, a, s);
-    case 2: return fp32 ? launch_stage_t<2, float>(mode, g, T, a, s) : launch_stage_t<2, double>(mode, g, T, a, s);
-    case 3: return fp32 ? launch_stage_t<3, float>(mode, g, T, a, s) : launch_stage_t<3, double>(mode, g, T, a, s);
-    case 4: return fp32 ? launch_stage_t<4, float>(mode, g, T, a, s) : launch_stage_t<4, double>(mode, g, T, a, s);
+    case 1: return fp32 ? launch_stage_t<1, float>(scheme, mode, g, T, a, s) : launch_stage_t<1, double>(scheme, mode, g, T, a, s);
+    case 2: return fp32 ? launch_stage_t<2, float>(scheme, mode, g, T, a, s) : launch_stage_t<2, double>(scheme, mode, g, T, a, s);
+    case 3: return fp32 ? launch_stage_t<3, float>(scheme, mode, g, T, a, s) : launch_stage_t<3, double>(scheme, mode, g, T, a, s);
+    case 4: return fp32 ? launch_stage_t<4, float>(scheme, mode, g, T, a, s) : launch_stage_t<4, double>(scheme, mode, g, T, a, s);
     default: return hipErrorInvalidValue;
   }
 }

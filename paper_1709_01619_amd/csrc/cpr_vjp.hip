@@ -456,9 +456,11 @@ static hipError_t launch_vjp_t(const Geometry& g, const Tables1D& T, const VjpAr
   return hipGetLastError();
 }
 
-hipError_t launch_vjp(int P, bool fp32, const Geometry& g, const Tables1D& T, const VjpArgs& a,
-                      hipStream_t s) {
-  if (T.points != kGauss) return hipErrorInvalidValue;  // the transpose of the Gauss scheme only
+hipError_t launch_vjp(int P, bool fp32, int scheme, const Geometry& g, const Tables1D& T,
+                      const VjpArgs& a, hipStream_t s) {
+  // the transpose of the flux-interpolant schemes only (either point set:
+  // the face rows are used as given)
+  if (scheme == kSchemeGllChain || T.points != scheme_points(scheme)) return hipErrorInvalidValue;
   switch (P) {
     case 1: return fp32 ? launch_vjp_t<1, float>(g, T, a, s) : launch_vjp_t<1, double>(g, T, a, s);
     case 2: return fp32 ? launch_vjp_t<2, float>(g, T, a, s) : launch_vjp_t<2, double>(g, T, a, s);

@@ -17,7 +17,8 @@ from . import _lib
 
 BC = {"periodic": _lib.CPR_BC_PERIODIC, "transmissive": _lib.CPR_BC_TRANSMISSIVE}
 PRECISION = {"fp64": _lib.CPR_FP64, "fp32_bulk": _lib.CPR_FP32_BULK}
-SCHEME = {"gl_lp": _lib.CPR_SCHEME_GL_LP, "gll_chain": _lib.CPR_SCHEME_GLL_CHAIN}
+SCHEME = {"gl_lp": _lib.CPR_SCHEME_GL_LP, "gll_chain": _lib.CPR_SCHEME_GLL_CHAIN,
+          "gll_lp": _lib.CPR_SCHEME_GLL_LP}
 
 
 def _torch():
@@ -30,8 +31,9 @@ class Solver:
     scheme) bound to a GPU. States are float64 tensors of shape
     (4, ny, nx, P+1, P+1) on that GPU (see include/cpr.h for the layout).
     scheme: "gl_lp" (Gauss-Legendre points, derivative of the flux
-    interpolant) or "gll_chain" (the paper's CPR: Gauss-Lobatto points,
-    chain-rule divergence)."""
+    interpolant), "gll_chain" (the paper's CPR: Gauss-Lobatto points,
+    chain-rule divergence) or "gll_lp" (the paper's NDG: Gauss-Lobatto
+    points, derivative of the flux interpolant)."""
 
     def __init__(self, P, nx, ny, x0=0.0, x1=10.0, y0=0.0, y1=10.0, bc="periodic",
                  precision="fp64", gamma=1.4, limiter=False, tvb_m=10.0, cfl=0.0, t_end=0.0,

@@ -54,7 +54,7 @@ def test_config_struct_layout_matches_header():
 @pytest.mark.parametrize("field,value", [
     ("abi_version", 99), ("order_p", 0), ("order_p", 5), ("nx", 0), ("ny", -3),
     ("x1", 0.0), ("y1", -1.0), ("bc", 7), ("precision", 3), ("gamma", 1.0),
-    ("gamma", float("nan")), ("limiter", 2), ("scheme", 2), ("tvb_m", -1.0), ("cfl", -0.1),
+    ("gamma", float("nan")), ("limiter", 2), ("scheme", 3), ("tvb_m", -1.0), ("cfl", -0.1),
     ("t_end", float("inf")), ("nx", (1 << 20) + 1),
 ])
 def test_init_rejects_invalid_config_without_gpu(field, value):
@@ -120,5 +120,6 @@ def test_library_lobatto_tables_agree_with_oracle(P):
     np.testing.assert_allclose(gr, T.gRp, atol=1e-13)
     # the default scheme's tables are cpr_tables' own
     assert L.tables(P, L.CPR_SCHEME_GL_LP) == L.tables(P)
-    assert lib.cpr_scheme_tables(2, P, None, None, None, None) == L.CPR_EINVAL
+    assert L.tables(P, L.CPR_SCHEME_GLL_LP) == L.tables(P, L.CPR_SCHEME_GLL_CHAIN)
+    assert lib.cpr_scheme_tables(3, P, None, None, None, None) == L.CPR_EINVAL
     assert lib.cpr_scheme_tables(L.CPR_SCHEME_GLL_CHAIN, 5, None, None, None, None) == L.CPR_EINVAL

@@ -16,7 +16,7 @@ import pytest
 
 import inputs
 from oracle import cpr, euler, limiter, tables
-from tests.golden_data import PAPER_L2_RTOL, paper_vortex_l2
+from tests.golden_data import PAPER_COLUMN, PAPER_L2_RTOL, paper_vortex_l2
 from tests.gpu_util import dev, host, make_solver, rel_err, say, torch
 from tests.test_gpu_limiter_adjoint import _blurred_riemann, _margins
 
@@ -167,19 +167,21 @@ def _gpu_run_to_one(g, cfl):
 ROWS = paper_vortex_l2()
 
 
-@pytest.mark.parametrize("P,n,cfl,cpr_err,dg_err", ROWS)
-@pytest.mark.parametrize("scheme", [CH, cpr.GL_LP])
-def test_paper_smooth_problem_errors(scheme, P, n, cfl, cpr_err, dg_err):
+@pytest.mark.parametrize("row", ROWS, ids=lambda r: f"P{r[0]}-{r[1]}")
+@pytest.mark.parametrize("scheme", cpr.SCHEMES)
+def test_paper_smooth_problem_errors(scheme, row):
     """Tables 2 and 3: the chain-rule scheme reproduces the paper's CPR
-    errors and the Gauss-Legendre scheme its DG errors, on every mesh the
-    tables list, through the device CFL stepping."""
+    errors, the Gauss-Legendre scheme its DG errors and the Lobatto scheme
+    with the flux derivative its NDG errors, on every mesh the tables list,
+    through the device CFL stepping."""
+    P, n, cfl = row[:3]
     g = cpr.Grid(P=P, nx=n, ny=n, x0=-5.0, x1=5.0, y0=-5.0, y1=5.0, scheme=scheme)
     say("paper smooth problem", scheme, P, n)
     s, qd = _gpu_run_to_one(g, cfl)
     x, y = g.coords()
     exact = dev(_paper_vortex().conserved(x, y, 1.0))
     got = s.l2_diff(qd, exact, 0)
-    want = cpr_err if scheme == CH else dg_err
+    want = row[PAPER_COLUMN[scheme]]
     print(f"{scheme} P={P} {n}x{n}: L2 {got:.4e} (paper {want:.3e})")
     assert abs(got - want) <= PAPER_L2_RTOL * want
 

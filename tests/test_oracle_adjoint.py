@@ -38,8 +38,9 @@ def test_rusanov_vjp_dot_product(axis):
 
 @pytest.mark.parametrize("P", [1, 2, 3, 4])
 @pytest.mark.parametrize("bc", ["periodic", "transmissive"])
-def test_residual_vjp_dot_product(P, bc):
-    g = cpr.Grid(P=P, nx=3, ny=4, x0=0.0, x1=1.5, y0=0.0, y1=2.0, bc=bc)
+@pytest.mark.parametrize("scheme", [cpr.GL_LP, cpr.GLL_LP])
+def test_residual_vjp_dot_product(P, bc, scheme):
+    g = cpr.Grid(P=P, nx=3, ny=4, x0=0.0, x1=1.5, y0=0.0, y1=2.0, bc=bc, scheme=scheme)
     q = inputs.random_state((g.ny, g.nx, g.n1, g.n1), seed=60 + P)
     rng = np.random.default_rng(70 + P)
     for _ in range(3):
@@ -101,3 +102,10 @@ def test_gradient_matches_central_differences():
         fd = (Jof(q0 + h * d) - Jof(q0 - h * d)) / (2 * h)
         ad = np.sum(grad * d)
         assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+
+
+def test_chain_rule_scheme_has_no_transpose():
+    g = cpr.Grid(P=2, nx=2, ny=2, scheme=cpr.GLL_CHAIN)
+    q = inputs.random_state((2, 2, 3, 3), seed=1)
+    with pytest.raises(NotImplementedError):
+        adjoint.residual_vjp(q, q, g)
