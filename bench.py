@@ -23,6 +23,9 @@ Printed: one JSON line (rank 0). Extra objects:
                 chain-rule divergence): stage timings, and the paper's
                 smooth-problem errors (Tables 2 and 3) reproduced by both
                 schemes.
+  paper_radial_shock_tube  the paper's discontinuous problem on its meshes:
+                steps, time to solution and distance from the 1D radial
+                reference for both schemes.
 """
 
 from __future__ import annotations
@@ -258,34 +261,39 @@ def adjoint_p4():
 
 
 def paper_scheme():
-    """The paper's own CPR (Gauss-Lobatto points, chain-rule divergence):
-    its stage kernel on the headline workload (P=3 256^2, FP64 and
-    FP32-bulk) and on P=4 1024^2, and the paper's smooth-problem protocol
-    (vortex of strength 5, mean flow (1,1,0,1), periodic [-5,5]^2, CFL of
-    Table 1, device CFL steps to t=1) for both schemes against the errors
-    of Tables 2 and 3 (CPR column for the chain rule, DG column for the
-    Gauss-Legendre scheme)."""
+    """The paper's own CPR (Gauss-Lobatto points, chain-rule divergence)
+    and its NDG (Gauss-Lobatto points, flux derivative): their stage kernels
+    on the headline workload (P=3 256^2) and on P=4 1024^2, and the paper's
+    smooth-problem protocol (vortex of strength 5, mean flow (1,1,0,1),
+    periodic [-5,5]^2, CFL of Table 1, device CFL steps to t=1) for the
+    three schemes against the errors of Tables 2 and 3 (CPR column for the
+    chain rule, DG column for the Gauss-Legendre scheme, NDG column for the
+    Gauss-Lobatto flux-derivative scheme)."""
     import torch
     import inputs
     from paper_1709_01619_amd import Solver
     from tests.golden_data import paper_vortex_l2
-    out = {"scheme": "gll_chain"}
-    for P, n, steps, prec in ((3, 256, 300, "fp64"), (3, 256, 300, "fp32_bulk"),
-                              (4, 1024, 20, "fp64")):
-        s = Solver(P, n, n, precision=prec, scheme="gll_chain")
+    out = {"scheme": "gll_chain (CPR); gll_lp (NDG) where named"}
+    for scheme, P, n, steps, prec in (("gll_chain", 3, 256, 300, "fp64"),
+                                      ("gll_chain", 3, 256, 300, "fp32_bulk"),
+                                      ("gll_chain", 4, 1024, 20, "fp64"),
+                                      ("gll_lp", 3, 256, 300, "fp64"),
+                                      ("gll_lp", 4, 1024, 20, "fp64")):
+        s = Solver(P, n, n, precision=prec, scheme=scheme)
         q = vortex_state(s)
         dt = 1e-4 if n == 1024 else c2_dt(s, q)[0]
         ms = time_steps(s, q, dt, steps, 5)
         s.sync()
         U = s.n_unknowns
         ach = BYTES_PER_UNKNOWN_STEP / 3.0 * U / (ms * 1e-3 / 3.0) / 1e9
-        out[f"p{P}_{n}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": 3.0 * U / (ms * 1e-3),
-                                   "hbm_frac": round(ach / HBM_PEAK_GBS, 4)}
-        log("chain", P, n, prec, out[f"p{P}_{n}_{prec}"])
+        key = f"p{P}_{n}_{prec}" + ("_ndg" if scheme == "gll_lp" else "")
+        out[key] = {"ms_per_step": ms, "dof_updates_per_s": 3.0 * U / (ms * 1e-3),
+                    "hbm_frac": round(ach / HBM_PEAK_GBS, 4)}
+        log(scheme, P, n, prec, out[key])
         del s, q
     V = inputs.Vortex(eps=5.0, lo=-5.0, hi=5.0, u_inf=1.0, v_inf=0.0, center=(0.0, 0.0))
     rows = []
-    for scheme, col in (("gll_chain", 3), ("gl_lp", 4)):
+    for scheme, col in (("gll_chain", 3), ("gl_lp", 4), ("gll_lp", 5)):
         prev = None
         for r in paper_vortex_l2():
             P, n, cfl = r[0], r[1], r[2]
@@ -318,6 +326,69 @@ def paper_scheme():
     return out
 
 
+def radial_tube():
+    """The paper's discontinuous problem: the radially expanding shock tube
+    of Section 4 (rho = p = 1 inside r = 0.4, rho = 0.125, p = 0.1 outside,
+    at rest) on [-1,1]^2, transmissive, TVB limiter (M = 10) after every
+    stage, CFL of Table 4 (0.2 for P1, 0.1 for P2), device dt, to t = 0.25,
+    on the paper's 200^2 and 400^2 meshes, both schemes: steps, time to
+    solution, troubled fraction, and the L1 distance of the density from the
+    one-dimensional radial reference solution (4000 cells)."""
+    import numpy as np
+    import torch
+    import inputs
+    from paper_1709_01619_amd import Solver
+    from tests import radial_ref
+    rc, rho_ref = radial_ref.solve(0.25, n=4000)[:2]
+    rows = []
+    for scheme, P, cfl in (("gll_chain", 1, 0.2), ("gll_chain", 2, 0.1), ("gl_lp", 1, 0.2),
+                           ("gl_lp", 2, 0.1)):
+        for n in (200, 400):
+            s = Solver(P, n, n, -1.0, 1.0, -1.0, 1.0, bc="transmissive", limiter=True,
+                       tvb_m=10.0, cfl=cfl, t_end=0.25, scheme=scheme)
+            x, y = s.coords()
+            xn, yn = x.cpu().numpy(), y.cpu().numpy()
+            q = torch.from_numpy(inputs.radial_shock_tube(xn, yn)).cuda()
+            s.set_time(0.0)
+            s.limit(q)
+            s.troubled_total(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            steps, t = 0, 0.0
+            while t < 0.2 and steps < 20000:
+                for _ in range(20):
+                    s.step(q, 0.0, limit=True)
+                steps += 20
+                t, _ = s.get_time()
+            while t < 0.25 * (1 - 1e-14) and steps < 20000:
+                s.step(q, 0.0, limit=True)
+                steps += 1
+                t, _ = s.get_time()
+            el = time.perf_counter() - t0
+            qh = q.cpu().numpy()
+            W = s.quad_weights().cpu().numpy()
+            w1 = np.asarray(_lib_tables(P, scheme)[1])
+            l1, l1c = radial_ref.metrics(qh[0], xn, yn, W, w1, rc, rho_ref)
+            total = s.troubled_total()
+            rows.append({"scheme": scheme, "P": P, "mesh": n, "cfl": cfl,
+                         "dofs_per_variable": n * n * (P + 1) ** 2, "steps": steps, "t": t,
+                         "s_to_solution": el, "s_per_step": el / steps,
+                         "troubled_fraction_mean": total / (3.0 * steps * n * n),
+                         "l1_rho_vs_radial_reference": l1, "l1_rho_centre_row": l1c,
+                         "rho_min": float(qh[0].min()), "rho_max": float(qh[0].max())})
+            log("radial tube", rows[-1])
+            del s, q
+    return {"workload": "radially expanding shock tube (paper Section 4), [-1,1]^2, "
+                        "transmissive, TVB M=10 after every stage, Table 4 CFL, to t=0.25",
+            "cases": rows}
+
+
+def _lib_tables(P, scheme):
+    from paper_1709_01619_amd import _lib
+    from paper_1709_01619_amd.solver import SCHEME
+    return _lib.tables(P, SCHEME[scheme])
+
+
 def profile_legs(a):
     """Run selected legs only (used under rocprofv3): no JSON line."""
     import torch
@@ -340,11 +411,13 @@ def profile_legs(a):
             ms = time_steps(s, q, dt, a.steps, a.warmup)
             print(f"main P=3 256^2 {prec}: {ms:.4f} ms/step", flush=True)
     if "chain" in legs:
-        for P, n, prec in ((3, 256, "fp64"), (3, 256, "fp32_bulk"), (4, 1024, "fp64")):
-            s = Solver(P, n, n, precision=prec, scheme="gll_chain")
+        for scheme, P, n, prec in (("gll_chain", 3, 256, "fp64"), ("gll_chain", 3, 256, "fp32_bulk"),
+                                   ("gll_chain", 4, 1024, "fp64"), ("gll_lp", 3, 256, "fp64"),
+                                   ("gll_lp", 4, 1024, "fp64")):
+            s = Solver(P, n, n, precision=prec, scheme=scheme)
             q = vortex_state(s)
             ms = time_steps(s, q, 1e-4, a.steps, a.warmup)
-            print(f"chain P={P} {n}^2 {prec}: {ms:.4f} ms/step", flush=True)
+            print(f"chain {scheme} P={P} {n}^2 {prec}: {ms:.4f} ms/step", flush=True)
     if "scale" in legs:
         for prec in ("fp64", "fp32_bulk"):
             s = Solver(4, 1024, 1024, precision=prec)
@@ -402,7 +475,7 @@ def main(argv=None):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "cpr::stage_kernel<3,double,0,false>",
+                "kernel": "cpr::stage_kernel<3,double,0,0>",
                 "note": "256^2 P=3 states are 33.6 MB each, so the three live states fit the "
                         "256 MB Infinity Cache; see scale_p4_1024 for an HBM-resident case"}
 
@@ -491,6 +564,7 @@ def main(argv=None):
         log("c3", extra["c3_limited_riemann"])
         extra["c5_adjoint"] = adjoint_p4()
         extra["paper_cpr_gll_chain"] = paper_scheme()
+        extra["paper_radial_shock_tube"] = radial_tube()
     copy_gbs = copy_bandwidth()
     roofline["copy_gbs"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)

@@ -117,6 +117,24 @@ def riemann_quadrants(x, y, gamma=GAMMA, split=(0.5, 0.5), states=None):
 
 
 # ----------------------------------------------------------------------------
+# Radially expanding shock tube on [-1,1]^2 (the paper's discontinuous
+# problem, Section 4, after Toro): rho = p = 1 inside the circle r < 0.4,
+# rho = 0.125, p = 0.1 outside, fluid at rest.
+# ----------------------------------------------------------------------------
+
+def radial_shock_tube(x, y, gamma=GAMMA, radius=0.4, inside=(1.0, 1.0),
+                      outside=(0.125, 0.1)):
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    r2 = x * x + y * y
+    inner = r2 < radius * radius
+    rho = np.where(inner, inside[0], outside[0])
+    p = np.where(inner, inside[1], outside[1])
+    zero = np.zeros_like(rho)
+    return conserved_from_primitive(rho, zero, zero, p, gamma)
+
+
+# ----------------------------------------------------------------------------
 # Entropy (density) wave: rho = 1 + a sin(2 pi (x+y)/L), u = v = 1, p = 1,
 # advected unchanged; a smooth periodic field with no vortex tail.
 # ----------------------------------------------------------------------------
