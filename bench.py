@@ -321,6 +321,19 @@ def paper_scheme():
                          "slope": slope, "s_to_solution": el})
             del s, q, ex
     out["paper_smooth_problem"] = rows
+    # the paper's maximum-CFL convention (halve the CFL; admissible if the
+    # error moves by less than 0.1 %) on its smooth problem at 20x20
+    from paper_1709_01619_amd import cfl_search
+    mc = {}
+    for scheme in ("gll_chain", "gl_lp", "gll_lp"):
+        for P, start in ((1, 0.40), (2, 0.25)):
+            c, rec = cfl_search.max_cfl(
+                lambda x, P=P, scheme=scheme: cfl_search.vortex_error(P, 20, scheme, x), start)
+            mc[f"{scheme}_p{P}"] = {"max_cfl": c, "cfl_tried": [r[0] for r in rec]}
+    out["max_cfl_20x20"] = mc
+    out["max_cfl_table1"] = {"cpr_p1": 0.24, "cpr_p2": 0.14, "dg_p1": 0.24, "dg_p2": 0.14,
+                             "ndg_p1": 0.24, "ndg_p2": 0.14}
+    log("max cfl", mc)
     out["max_abs_log_ratio_to_paper"] = max(abs(math.log(r["ratio_to_paper"])) for r in rows)
     log("paper smooth problem", json.dumps(rows))
     return out
