@@ -69,6 +69,12 @@ def load(path: str = LIB_PATH):
         raise ImportError(
             f"{path} is missing: build the HIP library first "
             "(python -m paper_1709_01619_amd.build)")
+    try:
+        # torch carries its own HIP runtime; it must be loaded first, so
+        # that the library binds to the process's one runtime
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = POINTER
     sig = {

@@ -95,6 +95,8 @@ cpr_status stage(cpr_ctx* c, int mode, const double* src, const double* qn, doub
   s.dt_dev = device_dt ? c->dscal + 1 : nullptr;
   s.skip = device_dt ? c->iscr + 1 : nullptr;
   s.err = c->iscr;
+  const uintptr_t any = (uintptr_t)src | (uintptr_t)qn | (uintptr_t)dst | (uintptr_t)rout;
+  s.vec = (any & 15) == 0;
   HIP_TRY(c, launch_stage(c->cfg.order_p, c->cfg.precision == CPR_FP32_BULK, c->cfg.scheme, mode,
                           c->geo, c->tab, s, c->stream),
           "stage kernel launch");

@@ -57,6 +57,7 @@ struct StageArgs {
   const double* dt_dev;  // when non-null, dt is read from here
   const int* skip;       // when non-null and *skip != 0, the kernel does nothing
   int* err;              // set to 1 on a non-physical state
+  int vec;               // every state pointer is 16-byte aligned
 };
 
 enum { kStageRK = 0, kStageResidual = 1 };

@@ -99,16 +99,25 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   // outside neighbour lines, all loads issued before any is consumed ----
   {
     double v[TC::NRUN][TC::NIT];
+    double2 v2[TC::NRUN][TC::NIT2];
 #pragma unroll
     for (int u = 0; u < TC::NRUN; ++u) {
       const int sg = TC::run(wv, u);
       const int k = sg >> 3, cy = sg & 7;
       const bool ok = sg < 4 * kTile && cy < nay;
       const double* src = A.q_src + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+      if (TC::PAIRS && A.vec) {
 #pragma unroll
-      for (int it = 0; it < TC::NIT; ++it) {
-        const int f = it * 64 + lane;
-        if (ok && f < seg_len) v[u][it] = src[f];
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          if (ok && f < seg_len) v2[u][it] = *reinterpret_cast<const double2*>(src + f);
+        }
+      } else {
+#pragma unroll
+        for (int it = 0; it < TC::NIT; ++it) {
+          const int f = it * 64 + lane;
+          if (ok && f < seg_len) v[u][it] = src[f];
+        }
       }
     }
     double hraw[4][N1];
@@ -157,10 +166,21 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       const int k = sg >> 3, cy = sg & 7;
       const bool ok = sg < 4 * kTile && cy < nay;
       double* dst = qs + k * VS + cy * kTile * S;
+      if (TC::PAIRS && A.vec) {
 #pragma unroll
-      for (int it = 0; it < TC::NIT; ++it) {
-        const int f = it * 64 + lane;
-        if (ok && f < seg_len) dst[tc.loff[it]] = v[u][it];
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          if (ok && f < seg_len) {
+            dst[tc.loff2[it]] = v2[u][it].x;
+            dst[tc.loff2[it] + 1] = v2[u][it].y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int it = 0; it < TC::NIT; ++it) {
+          const int f = it * 64 + lane;
+          if (ok && f < seg_len) dst[tc.loff[it]] = v[u][it];
+        }
       }
     }
     if (LOB && halo && hact && hout) {
@@ -349,55 +369,109 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   // all of a wave's q_n loads are issued before its stores, which may
   // overwrite q_n in place
   const bool need_qn = MODE == kStageRK && A.a != 0.0;
-  double vn[TC::NRUN][TC::NIT];
+  if (TC::PAIRS && A.vec) {
+    // the same in pairs of values (16-byte accesses)
+    double2 vn[TC::NRUN][TC::NIT2];
 #pragma unroll
-  for (int u = 0; u < TC::NRUN; ++u) {
-    const int sg = TC::run(wv, u);
-    const int k = sg >> 3, cy = sg & 7;
-    const bool ok = need_qn && sg < 4 * kTile && cy < nay;
-    const double* src = A.q_n + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = need_qn && sg < 4 * kTile && cy < nay;
+      const double* src = A.q_n + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
 #pragma unroll
-    for (int it = 0; it < TC::NIT; ++it) {
-      const int f = it * 64 + lane;
-      if (ok && f < seg_len) vn[u][it] = src[f];
-    }
-  }
-  // every output value of the wave is formed before the first store: a
-  // store issued between two uses of loaded data would make the later use
-  // wait for the store as well
-#pragma unroll
-  for (int u = 0; u < TC::NRUN; ++u) {
-    const int sg = TC::run(wv, u);
-    const int cy = sg & 7, k = sg >> 3;
-    const bool ok = sg < 4 * kTile && cy < nay;
-    const double* img = qs + k * VS + cy * kTile * S;
-#pragma unroll
-    for (int it = 0; it < TC::NIT; ++it) {
-      const int f = it * 64 + lane;
-      if (ok && f < seg_len) {
-        const double v = img[tc.loff[it]];
-        vn[u][it] = need_qn ? fma(A.a, vn[u][it], v) : v;
+      for (int it = 0; it < TC::NIT2; ++it) {
+        const int f = 2 * (it * 64 + lane);
+        if (ok && f < seg_len) vn[u][it] = *reinterpret_cast<const double2*>(src + f);
       }
     }
-  }
-  // the loads above sit in lane-predicated blocks, after which the
-  // compiler cannot tell that they have all returned and would wait for
-  // every earlier store before each store; one explicit wait settles it
-  __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-  for (int u = 0; u < TC::NRUN; ++u) {
-    const int sg = TC::run(wv, u);
-    const int k = sg >> 3, cy = sg & 7;
-    const bool ok = sg < 4 * kTile && cy < nay;
-    const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int cy = sg & 7, k = sg >> 3;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const double* img = qs + k * VS + cy * kTile * S;
 #pragma unroll
-    for (int it = 0; it < TC::NIT; ++it) {
-      const int f = it * 64 + lane;
-      if (ok && f < seg_len) {
-        if (MODE == kStageRK)
-          A.q_dst[gb + f] = vn[u][it];
-        else
-          static_cast<R*>(A.r_out)[gb + f] = (R)vn[u][it];
+      for (int it = 0; it < TC::NIT2; ++it) {
+        const int f = 2 * (it * 64 + lane);
+        if (ok && f < seg_len) {
+          const double a0 = img[tc.loff2[it]], a1 = img[tc.loff2[it] + 1];
+          vn[u][it].x = need_qn ? fma(A.a, vn[u][it].x, a0) : a0;
+          vn[u][it].y = need_qn ? fma(A.a, vn[u][it].y, a1) : a1;
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT2; ++it) {
+        const int f = 2 * (it * 64 + lane);
+        if (ok && f < seg_len) {
+          if (MODE == kStageRK) {
+            *reinterpret_cast<double2*>(A.q_dst + gb + f) = vn[u][it];
+          } else {
+            R* ro = static_cast<R*>(A.r_out) + gb + f;
+            ro[0] = (R)vn[u][it].x;
+            ro[1] = (R)vn[u][it].y;
+          }
+        }
+      }
+    }
+  } else {
+    double vn[TC::NRUN][TC::NIT];
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = need_qn && sg < 4 * kTile && cy < nay;
+      const double* src = A.q_n + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) vn[u][it] = src[f];
+      }
+    }
+    // every output value of the wave is formed before the first store: a
+    // store issued between two uses of loaded data would make the later use
+    // wait for the store as well
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int cy = sg & 7, k = sg >> 3;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const double* img = qs + k * VS + cy * kTile * S;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) {
+          const double v = img[tc.loff[it]];
+          vn[u][it] = need_qn ? fma(A.a, vn[u][it], v) : v;
+        }
+      }
+    }
+    // the loads above sit in lane-predicated blocks, after which the
+    // compiler cannot tell that they have all returned and would wait for
+    // every earlier store before each store; one explicit wait settles it
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT; ++it) {
+        const int f = it * 64 + lane;
+        if (ok && f < seg_len) {
+          if (MODE == kStageRK)
+            A.q_dst[gb + f] = vn[u][it];
+          else
+            static_cast<R*>(A.r_out)[gb + f] = (R)vn[u][it];
+        }
       }
     }
   }

@@ -186,3 +186,33 @@ def test_residual_transpose_bitwise(P, prec, bc):
     r = host(s.residual(dev(q)))
     rt = host(s.residual(dev(qt)))
     assert np.array_equal(rt, r[[0, 2, 1, 3]].transpose(0, 2, 1, 4, 3))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
+@pytest.mark.parametrize("P", [2, 3])
+def test_misaligned_states_match_aligned(P, prec):
+    """States that are not 16-byte aligned take the kernel's 8-byte copies
+    (at P=3 aligned ones move pairs of values); the results are the same bit
+    for bit, for the input, the residual output and the RK stages."""
+    t = torch()
+    g = cpr.Grid(P=P, nx=13, ny=11, x0=0.0, x1=2.0, y0=0.0, y1=1.5)
+    q = inputs.random_state((11, 13, P + 1, P + 1), seed=880 + P)
+    say("misaligned states", P, prec)
+    s = make_solver(g, precision=prec)
+    qa = dev(q)
+    buf = t.empty(q.size + 1, dtype=t.float64, device="cuda")
+    qm = buf[1:].view(q.shape)
+    qm.copy_(qa)
+    assert qa.data_ptr() % 16 == 0 and qm.data_ptr() % 16 == 8
+    rdt = t.float32 if prec == "fp32_bulk" else t.float64
+    rbuf = t.empty(q.size + 2, dtype=rdt, device="cuda")
+    rm_out = rbuf[1:1 + q.size].view(q.shape)
+    ra = host(s.residual(qa))
+    rm = host(s.residual(qm, out=rm_out))
+    assert np.array_equal(ra, rm)
+    if prec == "fp64":
+        assert rel_err(ra, cpr.residual(q, g)) <= 1e-12
+    for _ in range(2):
+        s.step(qa, 1e-3)
+        s.step(qm, 1e-3)
+    assert np.array_equal(host(qa), host(qm))
