@@ -174,6 +174,29 @@ def copy_bandwidth(reps=5):
     return 2.0 * n * 8 / ts[len(ts) // 2] / 1e9
 
 
+def stream_bandwidth(n_values, reps=20):
+    """out = a + 0.5 b over float64 arrays of n_values (read two, write one:
+    the traffic shape of an RK stage), median of reps, in GB/s: the
+    practical bandwidth ceiling at the size of one state."""
+    import torch
+    a = torch.rand(n_values, dtype=torch.float64, device="cuda")
+    b = torch.rand_like(a)
+    c = torch.empty_like(a)
+    torch.add(a, b, alpha=0.5, out=c)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.add(a, b, alpha=0.5, out=c)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    ts.sort()
+    del a, b, c
+    return 24.0 * n_values / ts[len(ts) // 2] / 1e9
+
+
 def small_config():
     """P=2 vortex on 20x20 elements, dt=1e-3, 100 steps: launch-latency
     regime (14400 unknowns)."""
@@ -581,7 +604,12 @@ def main(argv=None):
     copy_gbs = copy_bandwidth()
     roofline["copy_gbs"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
-    log("copy", copy_gbs)
+    stream_gbs = stream_bandwidth(U)
+    roofline["stream_gbs"] = round(stream_gbs, 1)
+    roofline["frac_of_stream"] = round(achieved / stream_gbs, 4)
+    roofline["stream_note"] = ("stream_gbs: torch out = a + 0.5 b on float64 arrays of one "
+                               "state's size (read two, write one, the shape of an RK stage)")
+    log("copy", copy_gbs, "stream", stream_gbs)
 
     cpu = None
     if not a.no_cpu:
