@@ -17,8 +17,10 @@
 // is the mean of both sides' gradients). The two sides' contributions of an interior
 // face are exchanged between adjacent lanes by wave shuffles; tile-boundary
 // faces are finished by boundary lanes that read the neighbour element's line
-// of q and v from global memory. The paper (arXiv:1709.01619) has no
-// adjoint; this transposes its Section 2.2 residual operator.
+// of q and v from global memory. Divisions use the forward kernels'
+// reciprocal (hardware estimate and two Newton steps, about 1 ulp). The
+// paper (arXiv:1709.01619) has no adjoint; this transposes its Section 2.2
+// residual operator.
 #include "cpr_device.h"
 
 namespace cpr {
@@ -27,7 +29,7 @@ namespace cpr {
 template <int AX, typename R>
 __device__ __forceinline__ void flux_jac_t(const R q[4], R gam, const R s[4], R out[4]) {
   constexpr int n = 1 + AX, t = 2 - AX;
-  const R ir = R(1) / q[0];
+  const R ir = recip(q[0]);
   const R un = q[n] * ir, ut = q[t] * ir;
   const R gm1 = gam - R(1);
   const R ke = R(0.5) * (un * un + ut * ut);
@@ -44,11 +46,11 @@ __device__ __forceinline__ void flux_jac_t(const R q[4], R gam, const R s[4], R 
 template <int AX, typename R>
 __device__ __forceinline__ void wave_speed_grad(const R q[4], R gam, R c, R g[4]) {
   constexpr int n = 1 + AX, t = 2 - AX;
-  const R ir = R(1) / q[0];
+  const R ir = recip(q[0]);
   const R un = q[n] * ir, ut = q[t] * ir;
   const R gg = gam * (gam - R(1));
   const R sgn = un >= R(0) ? R(1) : R(-1);
-  const R i2c = R(0.5) / c;
+  const R i2c = R(0.5) * recip(c);
   g[0] = gg * (-q[3] * ir * ir + (un * un + ut * ut) * ir) * i2c - sgn * un * ir;
   g[n] = -gg * un * ir * i2c + sgn * ir;
   g[t] = -gg * ut * ir * i2c;
@@ -61,7 +63,7 @@ __device__ __forceinline__ void rusanov_vjp(const R qL[4], const R qR[4], const 
                                             R cL[4], R cR[4], bool& bad) {
   constexpr int n = 1 + AX;
   const R gm1 = gam - R(1);
-  const R irL = R(1) / qL[0], irR = R(1) / qR[0];
+  const R irL = recip(qL[0]), irR = recip(qR[0]);
   const R pL = gm1 * (qL[3] - R(0.5) * (qL[1] * qL[1] + qL[2] * qL[2]) * irL);
   const R pR = gm1 * (qR[3] - R(0.5) * (qR[1] * qR[1] + qR[2] * qR[2]) * irR);
   const R cLs = sqrt_pos(gam * pL * irL), cRs = sqrt_pos(gam * pR * irR);
