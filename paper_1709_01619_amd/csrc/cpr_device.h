@@ -244,24 +244,24 @@ __device__ __forceinline__ void line_ops_chain(const R q[4][N1], const KTab<R, N
 // of the workgroup (wave w takes runs w, w+N1, ...); within a run, lane l
 // of pass it handles value it*64+l. All loads of a wave are issued before
 // any of them is consumed, so one memory round trip covers the whole copy.
-// With an even number of points per element, runs of at least 128 values
-// (PAIRS) and 16-byte aligned states, a lane moves two neighbouring values
-// of one element per access
-// instead (pass it, lane l: values 2(it*64+l) and the next), which halves
-// the memory instructions; the two share an element, so their LDS slots
-// are adjacent.
+// With runs of at least 64 values (PAIRS), 16-byte aligned states and even
+// run offsets, a lane moves two neighbouring values per access instead
+// (pass it, lane l: values 2(it*64+l) and the next), which halves the
+// memory instructions. With an odd number of points per element the two
+// may lie in neighbouring elements, so each has its own LDS slot.
 template <int N1, int S>
 struct TileCopy {
   static constexpr int NSP = N1 * N1;
   static constexpr int SEG = kTile * NSP;          // values in a full run
   static constexpr int NIT = (SEG + 63) / 64;      // passes per run
   static constexpr int NRUN = (4 * kTile + N1 - 1) / N1;  // runs per wave
-  // pairs only where a run fills a wave with them (P = 3); at P = 1 they
-  // would leave half the lanes idle and cost registers
-  static constexpr bool PAIRS = NSP % 2 == 0 && SEG >= 128;
+  // pairs where a run holds at least 64 values (P >= 2); at P = 1 they
+  // would leave most lanes idle and cost registers
+  static constexpr bool PAIRS = SEG >= 64;
   static constexpr int NIT2 = (SEG / 2 + 63) / 64;  // passes per run, in pairs
   int loff[NIT];    // LDS offset, within its run, of the value a lane moves
-  int loff2[NIT2];  // the same for the first value of a lane's pair
+  int loff2[NIT2];   // the same for the first value of a lane's pair
+  int loff2b[NIT2];  // and for its second
   __device__ __forceinline__ explicit TileCopy(int lane) {
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -274,6 +274,8 @@ struct TileCopy {
       const int f = 2 * (it * 64 + lane);
       const int cx = f / NSP;
       loff2[it] = cx * S + (f - cx * NSP);
+      const int cx2 = (f + 1) / NSP;
+      loff2b[it] = cx2 * S + (f + 1 - cx2 * NSP);
     }
   }
   // run u of wave wv: variable k, tile row cy; valid when sg < 4*kTile.

@@ -88,6 +88,14 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   using TC = TileCopy<N1, S>;
   const TC tc(lane);
   const int seg_len = nax * NSP;
+  // paired copies where they pay: float64 from P = 2, float32 only with an
+  // even number of points per element (its odd-P kernels lose occupancy to
+  // the pair registers and run slower)
+  constexpr bool PAIRS = TC::PAIRS && (sizeof(R) == 8 || NSP % 2 == 0);
+  // paired copies need 16-byte aligned states (A.vec), even run offsets
+  // (always when NSP is even; with NSP odd when nx is even, which makes
+  // planes, rows and tile starts even) and whole pairs (seg_len even)
+  const bool pairs_ok = A.vec && (NSP % 2 == 0 || (G.nx % 2 == 0 && seg_len % 2 == 0));
 
   // tile-boundary tasks: side hs (0 W, 1 E, 2 S, 3 N), position hp, line hm
   const bool halo = tid < 4 * kTile * N1;
@@ -106,7 +114,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       const int k = sg >> 3, cy = sg & 7;
       const bool ok = sg < 4 * kTile && cy < nay;
       const double* src = A.q_src + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
-      if (TC::PAIRS && A.vec) {
+      if (PAIRS && pairs_ok) {
 #pragma unroll
         for (int it = 0; it < TC::NIT2; ++it) {
           const int f = 2 * (it * 64 + lane);
@@ -166,13 +174,13 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       const int k = sg >> 3, cy = sg & 7;
       const bool ok = sg < 4 * kTile && cy < nay;
       double* dst = qs + k * VS + cy * kTile * S;
-      if (TC::PAIRS && A.vec) {
+      if (PAIRS && pairs_ok) {
 #pragma unroll
         for (int it = 0; it < TC::NIT2; ++it) {
           const int f = 2 * (it * 64 + lane);
           if (ok && f < seg_len) {
             dst[tc.loff2[it]] = v2[u][it].x;
-            dst[tc.loff2[it] + 1] = v2[u][it].y;
+            dst[tc.loff2b[it]] = v2[u][it].y;
           }
         }
       } else {
@@ -369,7 +377,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   // all of a wave's q_n loads are issued before its stores, which may
   // overwrite q_n in place
   const bool need_qn = MODE == kStageRK && A.a != 0.0;
-  if (TC::PAIRS && A.vec) {
+  if (PAIRS && pairs_ok) {
     // the same in pairs of values (16-byte accesses)
     double2 vn[TC::NRUN][TC::NIT2];
 #pragma unroll
@@ -394,7 +402,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       for (int it = 0; it < TC::NIT2; ++it) {
         const int f = 2 * (it * 64 + lane);
         if (ok && f < seg_len) {
-          const double a0 = img[tc.loff2[it]], a1 = img[tc.loff2[it] + 1];
+          const double a0 = img[tc.loff2[it]], a1 = img[tc.loff2b[it]];
           vn[u][it].x = need_qn ? fma(A.a, vn[u][it].x, a0) : a0;
           vn[u][it].y = need_qn ? fma(A.a, vn[u][it].y, a1) : a1;
         }

@@ -189,15 +189,18 @@ def test_residual_transpose_bitwise(P, prec, bc):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
-@pytest.mark.parametrize("P", [2, 3])
-def test_misaligned_states_match_aligned(P, prec):
-    """States that are not 16-byte aligned take the kernel's 8-byte copies
-    (at P=3 aligned ones move pairs of values); the results are the same bit
-    for bit, for the input, the residual output and the RK stages."""
+@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("nx", [13, 14])
+def test_misaligned_states_match_aligned(nx, P, prec):
+    """States that are not 16-byte aligned take the kernel's 8-byte copies;
+    aligned ones move pairs of values (float64 from P=2, float32 at P=3; with
+    an odd number of points per element only when nx is even). The results
+    are the same bit for bit, for the input, the residual output and the RK
+    stages."""
     t = torch()
-    g = cpr.Grid(P=P, nx=13, ny=11, x0=0.0, x1=2.0, y0=0.0, y1=1.5)
-    q = inputs.random_state((11, 13, P + 1, P + 1), seed=880 + P)
-    say("misaligned states", P, prec)
+    g = cpr.Grid(P=P, nx=nx, ny=11, x0=0.0, x1=2.0, y0=0.0, y1=1.5)
+    q = inputs.random_state((11, nx, P + 1, P + 1), seed=880 + P)
+    say("misaligned states", P, prec, nx)
     s = make_solver(g, precision=prec)
     qa = dev(q)
     buf = t.empty(q.size + 1, dtype=t.float64, device="cuda")
