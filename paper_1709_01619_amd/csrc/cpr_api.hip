@@ -130,6 +130,8 @@ cpr_status vjp(cpr_ctx* c, const double* q, const double* v, const double* x, co
   a.beta = beta;
   a.gam = gam;
   a.err = c->iscr;
+  const uintptr_t any = (uintptr_t)q | (uintptr_t)v | (uintptr_t)x | (uintptr_t)y | (uintptr_t)out;
+  a.vec = (any & 15) == 0;
   HIP_TRY(c, launch_vjp(c->cfg.order_p, c->cfg.precision == CPR_FP32_BULK, c->cfg.scheme, c->geo,
                         c->tab, a, c->stream),
           "adjoint kernel launch");

@@ -75,6 +75,7 @@ struct VjpArgs {
   double* out;
   double alpha, delta, beta, gam;
   int* err;
+  int vec;  // every state pointer is 16-byte aligned
 };
 hipError_t launch_vjp(int P, bool fp32, int scheme, const Geometry& g, const Tables1D& T,
                       const VjpArgs& a, hipStream_t s);

@@ -160,10 +160,46 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
   using TC = TileCopy<N1, S>;
   const TC tc(lane);
   const int seg_len = nax * NSP;
+  // paired 16-byte copies of q, v, x, y and out for float64, on the same
+  // conditions as in the stage kernel (aligned states, even run offsets,
+  // whole pairs)
+  constexpr bool PAIRS = TC::PAIRS && sizeof(R) == 8;
+  const bool pairs_ok = A.vec && (NSP % 2 == 0 || (G.nx % 2 == 0 && seg_len % 2 == 0));
 #pragma unroll
   for (int arr = 0; arr < 2; ++arr) {
     const double* gsrc = arr == 0 ? A.q : A.v;
     double* lds = arr == 0 ? qs : vs;
+    if (PAIRS && pairs_ok) {
+      double2 t2[TC::NRUN][TC::NIT2];
+#pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const double* src = gsrc + k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          if (ok && f < seg_len) t2[u][it] = *reinterpret_cast<const double2*>(src + f);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        double* dst = lds + k * VS + cy * kTile * S;
+#pragma unroll
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          if (ok && f < seg_len) {
+            dst[tc.loff2[it]] = t2[u][it].x;
+            dst[tc.loff2b[it]] = t2[u][it].y;
+          }
+        }
+      }
+      continue;
+    }
     double t[TC::NRUN][TC::NIT];
 #pragma unroll
     for (int u = 0; u < TC::NRUN; ++u) {
@@ -398,7 +434,61 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 
   // epilogue: the x and y loads of a wave are issued before its stores
   // (out may alias x)
-  {
+  if (PAIRS && pairs_ok) {
+    double2 xv[TC::NRUN][TC::NIT2], yv[TC::NRUN][TC::NIT2];
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT2; ++it) {
+        const int f = 2 * (it * 64 + lane);
+        const bool in = ok && f < seg_len;
+        xv[u][it] = (in && A.x != nullptr) ? *reinterpret_cast<const double2*>(A.x + gb + f)
+                                           : double2{0.0, 0.0};
+        yv[u][it] = (in && A.y != nullptr) ? *reinterpret_cast<const double2*>(A.y + gb + f)
+                                           : double2{0.0, 0.0};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const double* img = qs + k * VS + cy * kTile * S;
+#pragma unroll
+      for (int it = 0; it < TC::NIT2; ++it) {
+        const int f = 2 * (it * 64 + lane);
+        if (ok && f < seg_len) {
+          double o0 = img[tc.loff2[it]], o1 = img[tc.loff2b[it]];
+          if (A.x != nullptr) {
+            o0 += A.beta * xv[u][it].x;
+            o1 += A.beta * xv[u][it].y;
+          }
+          if (A.y != nullptr) {
+            o0 += A.gam * yv[u][it].x;
+            o1 += A.gam * yv[u][it].y;
+          }
+          xv[u][it] = double2{o0, o1};
+        }
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+    for (int u = 0; u < TC::NRUN; ++u) {
+      const int sg = TC::run(wv, u);
+      const int k = sg >> 3, cy = sg & 7;
+      const bool ok = sg < 4 * kTile && cy < nay;
+      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+      for (int it = 0; it < TC::NIT2; ++it) {
+        const int f = 2 * (it * 64 + lane);
+        if (ok && f < seg_len) *reinterpret_cast<double2*>(A.out + gb + f) = xv[u][it];
+      }
+    }
+  } else {
     double xv[TC::NRUN][TC::NIT], yv[TC::NRUN][TC::NIT];
 #pragma unroll
     for (int u = 0; u < TC::NRUN; ++u) {
