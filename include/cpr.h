@@ -168,6 +168,25 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
 cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt,
                             const double* lam_np1, double* lam_n);
 
+/* One unlimited SSP-RK3 step of size dt > 0 (as cpr_rk3_step with that dt
+ * and no limiter) that also hands back its stage states: q1 = qn + dt R(qn),
+ * q2 = 3/4 qn + 1/4 (q1 + dt R(q1)); q advances in place to q(n+1). For
+ * adjoint sweeps that keep the states of a checkpoint segment
+ * (cpr_adjoint_step_stages), which then need not recompute them. q, q1, q2:
+ * distinct device float64 states (CPR_EINVAL otherwise). */
+cpr_status cpr_rk3_step_stages(cpr_ctx* ctx, double* q, double dt, double* q1, double* q2);
+
+/* cpr_adjoint_step with the step's stage states q1, q2 supplied (from
+ * cpr_rk3_step_stages on q_n and the same dt) instead of recomputed: the
+ * three transposes only, lam2 = 2/3 (lam3 + dt J(q2)^T lam3),
+ * lam1 = 1/4 (lam2 + dt J(q1)^T lam2),
+ * lam_n = lam1 + dt J(qn)^T lam1 + 1/3 lam3 + 3/4 lam2. Same results, bit for
+ * bit, as cpr_adjoint_step. lam_n may alias lam_np1, not q_n, q1 or q2.
+ * CPR_EUNSUPPORTED as cpr_adjoint_step. */
+cpr_status cpr_adjoint_step_stages(cpr_ctx* ctx, const double* q_n, const double* q1,
+                                   const double* q2, double dt, const double* lam_np1,
+                                   double* lam_n);
+
 /* Largest sqrt(u^2+v^2) + c over all solution points of q (device);
  * synchronises; result to *out_host. */
 cpr_status cpr_max_wavespeed(cpr_ctx* ctx, const double* q, double* out_host);

@@ -24,7 +24,8 @@ CPR_SCHEME_GL_LP, CPR_SCHEME_GLL_CHAIN, CPR_SCHEME_GLL_LP = 0, 1, 2
 # exported symbols declared in include/cpr.h
 SYMBOLS = (
     "cpr_init", "cpr_destroy", "cpr_set_stream", "cpr_residual", "cpr_rk3_step", "cpr_limit",
-    "cpr_residual_vjp", "cpr_adjoint_step", "cpr_max_wavespeed", "cpr_integrals", "cpr_l2_diff",
+    "cpr_residual_vjp", "cpr_adjoint_step", "cpr_rk3_step_stages", "cpr_adjoint_step_stages",
+    "cpr_max_wavespeed", "cpr_integrals", "cpr_l2_diff",
     "cpr_point_coords", "cpr_tables", "cpr_scheme_tables", "cpr_set_time", "cpr_get_time", "cpr_troubled_total", "cpr_sync",
     "cpr_status_string", "cpr_last_error",
 )
@@ -86,6 +87,9 @@ def load(path: str = LIB_PATH):
         "cpr_limit": (c_int32, [c_void_p, c_void_p, c_void_p, P(c_int32)]),
         "cpr_residual_vjp": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "cpr_adjoint_step": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
+        "cpr_rk3_step_stages": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
+        "cpr_adjoint_step_stages": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                                              c_void_p, c_void_p]),
         "cpr_max_wavespeed": (c_int32, [c_void_p, c_void_p, P(c_double)]),
         "cpr_integrals": (c_int32, [c_void_p, c_void_p, P(c_double)]),
         "cpr_l2_diff": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, P(c_double)]),

@@ -331,29 +331,74 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
   return vjp(ctx, q, v, nullptr, nullptr, out, 0.0, 1.0, 0.0, 0.0);
 }
 
+namespace {
+
+cpr_status adjoint_checks(cpr_ctx* ctx, const char* who) {
+  if (ctx->cfg.limiter != CPR_LIM_NONE) {
+    set_err(ctx, "%s: the limiter is not differentiated", who);
+    return CPR_EUNSUPPORTED;
+  }
+  if (ctx->cfg.scheme == CPR_SCHEME_GLL_CHAIN) {
+    set_err(ctx, "%s: the chain-rule scheme is not differentiated", who);
+    return CPR_EUNSUPPORTED;
+  }
+  return CPR_OK;
+}
+
+// The three transposes of one SSP-RK3 step, given its stage states.
+cpr_status adjoint_sweep(cpr_ctx* ctx, const double* q_n, const double* q1, const double* q2,
+                         double dt, const double* lam_np1, double* lam_n) {
+  cpr_status st;
+  // lam2 = 2/3 (lam3 + dt J(q2)^T lam3)
+  if ((st = vjp(ctx, q2, lam_np1, nullptr, nullptr, ctx->lam2, 2.0 / 3.0, 2.0 / 3.0 * dt, 0.0, 0.0)) != CPR_OK) return st;
+  // lam1 = 1/4 (lam2 + dt J(q1)^T lam2)
+  if ((st = vjp(ctx, q1, ctx->lam2, nullptr, nullptr, ctx->lam1, 0.25, 0.25 * dt, 0.0, 0.0)) != CPR_OK) return st;
+  // lam_n = lam1 + dt J(qn)^T lam1 + 1/3 lam3 + 3/4 lam2
+  return vjp(ctx, q_n, ctx->lam1, lam_np1, ctx->lam2, lam_n, 1.0, dt, 1.0 / 3.0, 0.75);
+}
+
+}  // namespace
+
 cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt, const double* lam_np1,
                             double* lam_n) {
   if (ctx == nullptr || q_n == nullptr || lam_np1 == nullptr || lam_n == nullptr) return CPR_EINVAL;
   if (!(std::isfinite(dt) && dt > 0.0)) return CPR_EINVAL;
-  if (ctx->cfg.limiter != CPR_LIM_NONE) {
-    set_err(ctx, "cpr_adjoint_step: the limiter is not differentiated");
-    return CPR_EUNSUPPORTED;
-  }
-  if (ctx->cfg.scheme == CPR_SCHEME_GLL_CHAIN) {
-    set_err(ctx, "cpr_adjoint_step: the chain-rule scheme is not differentiated");
-    return CPR_EUNSUPPORTED;
-  }
+  cpr_status st = adjoint_checks(ctx, "cpr_adjoint_step");
+  if (st != CPR_OK) return st;
   if ((const double*)lam_n == q_n) return CPR_EINVAL;
-  cpr_status st;
   // recompute the stage states q1, q2 from q_n
   if ((st = stage(ctx, kStageRK, q_n, nullptr, ctx->q1, nullptr, 0.0, 1.0, dt, false)) != CPR_OK) return st;
   if ((st = stage(ctx, kStageRK, ctx->q1, q_n, ctx->q2, nullptr, 0.75, 0.25, dt, false)) != CPR_OK) return st;
-  // lam2 = 2/3 (lam3 + dt J(q2)^T lam3)
-  if ((st = vjp(ctx, ctx->q2, lam_np1, nullptr, nullptr, ctx->lam2, 2.0 / 3.0, 2.0 / 3.0 * dt, 0.0, 0.0)) != CPR_OK) return st;
-  // lam1 = 1/4 (lam2 + dt J(q1)^T lam2)
-  if ((st = vjp(ctx, ctx->q1, ctx->lam2, nullptr, nullptr, ctx->lam1, 0.25, 0.25 * dt, 0.0, 0.0)) != CPR_OK) return st;
-  // lam_n = lam1 + dt J(qn)^T lam1 + 1/3 lam3 + 3/4 lam2
-  return vjp(ctx, q_n, ctx->lam1, lam_np1, ctx->lam2, lam_n, 1.0, dt, 1.0 / 3.0, 0.75);
+  return adjoint_sweep(ctx, q_n, ctx->q1, ctx->q2, dt, lam_np1, lam_n);
+}
+
+cpr_status cpr_rk3_step_stages(cpr_ctx* ctx, double* q, double dt, double* q1, double* q2) {
+  if (ctx == nullptr || q == nullptr || q1 == nullptr || q2 == nullptr) return CPR_EINVAL;
+  if (!(std::isfinite(dt) && dt > 0.0)) return CPR_EINVAL;
+  if (q1 == q || q2 == q || q1 == q2) {
+    set_err(ctx, "cpr_rk3_step_stages: q, q1 and q2 must be distinct");
+    return CPR_EINVAL;
+  }
+  cpr_status st;
+  if ((st = stage(ctx, kStageRK, q, nullptr, q1, nullptr, 0.0, 1.0, dt, false)) != CPR_OK) return st;
+  if ((st = stage(ctx, kStageRK, q1, q, q2, nullptr, 0.75, 0.25, dt, false)) != CPR_OK) return st;
+  return stage(ctx, kStageRK, q2, q, q, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, false);
+}
+
+cpr_status cpr_adjoint_step_stages(cpr_ctx* ctx, const double* q_n, const double* q1,
+                                   const double* q2, double dt, const double* lam_np1,
+                                   double* lam_n) {
+  if (ctx == nullptr || q_n == nullptr || q1 == nullptr || q2 == nullptr || lam_np1 == nullptr ||
+      lam_n == nullptr)
+    return CPR_EINVAL;
+  if (!(std::isfinite(dt) && dt > 0.0)) return CPR_EINVAL;
+  cpr_status st = adjoint_checks(ctx, "cpr_adjoint_step_stages");
+  if (st != CPR_OK) return st;
+  if ((const double*)lam_n == q_n || (const double*)lam_n == q1 || (const double*)lam_n == q2) {
+    set_err(ctx, "cpr_adjoint_step_stages: lam_n must not alias q_n, q1 or q2");
+    return CPR_EINVAL;
+  }
+  return adjoint_sweep(ctx, q_n, q1, q2, dt, lam_np1, lam_n);
 }
 
 cpr_status cpr_max_wavespeed(cpr_ctx* ctx, const double* q, double* out_host) {

@@ -166,6 +166,25 @@ class Solver:
                                               self._ptr(out, name="lam_n")), "cpr_adjoint_step")
         return out
 
+    def step_stages(self, q, dt, q1, q2):
+        """One unlimited SSP-RK3 step of q in place that also writes its stage
+        states into q1 and q2 (cpr_rk3_step_stages)."""
+        self._enter()
+        self._check(self.lib.cpr_rk3_step_stages(self._ctx, self._ptr(q, name="q"), float(dt),
+                                                 self._ptr(q1, name="q1"),
+                                                 self._ptr(q2, name="q2")), "cpr_rk3_step_stages")
+
+    def adjoint_step_stages(self, q_n, q1, q2, dt, lam_np1, out=None):
+        """cpr_adjoint_step_stages: the adjoint step with the stage states
+        supplied."""
+        out = self.empty() if out is None else out
+        self._enter()
+        self._check(self.lib.cpr_adjoint_step_stages(
+            self._ctx, self._ptr(q_n, name="q_n"), self._ptr(q1, name="q1"),
+            self._ptr(q2, name="q2"), float(dt), self._ptr(lam_np1, name="lam_np1"),
+            self._ptr(out, name="lam_n")), "cpr_adjoint_step_stages")
+        return out
+
     def coords(self):
         torch = _torch()
         shp = (self.ny, self.nx, self.n1, self.n1)
@@ -232,10 +251,13 @@ class Solver:
 class Rollout:
     """nsteps unlimited SSP-RK3 steps of fixed dt as a differentiable map
     q0 -> q_T (torch.autograd.Function). The backward pass runs the
-    hand-written discrete adjoint (cpr_adjoint_step) step by step in reverse,
-    storing the state every ckpt_every steps in the forward pass and
-    recomputing each segment's states before sweeping it backwards, so that
-    memory holds one segment plus the checkpoints."""
+    hand-written discrete adjoint step by step in reverse, storing the state
+    every ckpt_every steps in the forward pass and recomputing each
+    segment's states before sweeping it backwards. The recomputation keeps
+    every step's two stage states too (cpr_rk3_step_stages), so that the
+    sweep runs only the three transposes per step
+    (cpr_adjoint_step_stages): memory holds three states per step of one
+    segment plus the checkpoints."""
 
     @staticmethod
     def apply(q0, solver: Solver, dt: float, nsteps: int, ckpt_every: int):
@@ -269,17 +291,21 @@ def _rollout_fn():
         def backward(ctx, grad):
             solver, dt, nsteps, C, ckpts = ctx.solver, ctx.dt, ctx.nsteps, ctx.C, ctx.ckpts
             lam = grad.detach().contiguous().clone()
-            seg = torch.empty((min(C, max(nsteps, 1)),) + tuple(solver.shape), dtype=torch.float64,
-                              device=solver.device)
+            # seg[i] = (q_n, q1, q2) of step s0 + i of the segment
+            seg = torch.empty((min(C, max(nsteps, 1)), 3) + tuple(solver.shape),
+                              dtype=torch.float64, device=solver.device)
+            nxt = torch.empty(tuple(solver.shape), dtype=torch.float64, device=solver.device)
             starts = list(range(0, nsteps, C))
             for s0 in reversed(starts):
                 s1 = min(s0 + C, nsteps)
-                seg[0].copy_(ckpts[s0])
-                for n in range(s0 + 1, s1):
-                    seg[n - s0].copy_(seg[n - s0 - 1])
-                    solver.step(seg[n - s0], dt)
-                for n in range(s1 - 1, s0 - 1, -1):
-                    solver.adjoint_step(seg[n - s0], dt, lam, out=lam)
+                seg[0, 0].copy_(ckpts[s0])
+                for i in range(s1 - s0):
+                    last = i == s1 - s0 - 1
+                    z = nxt if last else seg[i + 1, 0]   # q of the next step (unused after the last)
+                    z.copy_(seg[i, 0])
+                    solver.step_stages(z, dt, seg[i, 1], seg[i, 2])
+                for i in range(s1 - s0 - 1, -1, -1):
+                    solver.adjoint_step_stages(seg[i, 0], seg[i, 1], seg[i, 2], dt, lam, out=lam)
             return lam, None, None, None, None
 
     _ROLL = _Rollout
