@@ -160,10 +160,11 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
   using TC = TileCopy<N1, S>;
   const TC tc(lane);
   const int seg_len = nax * NSP;
-  // paired 16-byte copies of q, v, x, y and out for float64, on the same
-  // conditions as in the stage kernel (aligned states, even run offsets,
-  // whole pairs)
-  constexpr bool PAIRS = TC::PAIRS && sizeof(R) == 8;
+  // paired 16-byte copies of q, v, x, y and out (float64 states in both
+  // precisions), on the same conditions as in the stage kernel (aligned
+  // states, even run offsets, whole pairs); this kernel's LDS already holds
+  // it to one or two workgroups per CU, so the pair registers cost nothing
+  constexpr bool PAIRS = TC::PAIRS;
   const bool pairs_ok = A.vec && (NSP % 2 == 0 || (G.nx % 2 == 0 && seg_len % 2 == 0));
 #pragma unroll
   for (int arr = 0; arr < 2; ++arr) {

@@ -262,18 +262,19 @@ def test_rollout_gradient_fp32_bulk():
     assert rel <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
 @pytest.mark.parametrize("P", [2, 3, 4])
 @pytest.mark.parametrize("nx", [13, 14])
-def test_residual_vjp_misaligned_matches_aligned(nx, P):
+def test_residual_vjp_misaligned_matches_aligned(nx, P, prec):
     """A cotangent 8 bytes past a 16-byte boundary takes the transpose
-    kernel's 8-byte copies; aligned states move pairs (float64, P >= 2, and
-    for odd points per element only when nx is even). Same bits either way."""
+    kernel's 8-byte copies; aligned states move pairs (P >= 2, and for odd
+    points per element only when nx is even). Same bits either way."""
     t = torch()
     g = cpr.Grid(P=P, nx=nx, ny=9, x0=0.0, x1=2.0, y0=0.0, y1=1.5)
     q = inputs.random_state((9, nx, P + 1, P + 1), seed=5100 + P)
     v = np.random.default_rng(5200 + P).standard_normal(g.shape)
-    say("vjp misaligned", P, nx)
-    s = make_solver(g)
+    say("vjp misaligned", P, nx, prec)
+    s = make_solver(g, precision=prec)
     qd = dev(q)
     va = dev(v)
     buf = t.empty(v.size + 1, dtype=t.float64, device="cuda")
@@ -283,8 +284,9 @@ def test_residual_vjp_misaligned_matches_aligned(nx, P):
     oa = host(s.residual_vjp(qd, va))
     om = host(s.residual_vjp(qd, vm))
     assert np.array_equal(oa, om)
-    ref = adjoint.residual_vjp(q, v, g)
-    assert np.max(np.abs(oa - ref)) <= 1e-12 * np.max(np.abs(ref))
+    if prec == "fp64":
+        ref = adjoint.residual_vjp(q, v, g)
+        assert np.max(np.abs(oa - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 @pytest.mark.parametrize("P", [2, 3])
