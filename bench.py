@@ -149,7 +149,20 @@ def cpu_baseline(P=3, n=256, steps=None, budget_s=15.0):
                   f"({U} unknowns), NumPy float64, 1 BLAS thread, {el:.1f} s",
         "s_per_step": el / done,
         "host_cpus": os.cpu_count(),
+        "host_cpu_model": _cpu_model(),
+        "numpy_blas_threads": 1 if limiter is not None else None,
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def copy_bandwidth(reps=5):

@@ -83,8 +83,10 @@ cpr_status check_device_error(cpr_ctx* c) {
 }
 
 cpr_status stage(cpr_ctx* c, int mode, const double* src, const double* qn, double* dst,
-                 void* rout, double a, double b, double dt, bool device_dt) {
+                 void* rout, double a, double b, double dt, bool device_dt, bool means = false) {
   StageArgs s{};
+  s.qbar = means ? c->qbar : nullptr;
+  for (int i = 0; i <= c->cfg.order_p; ++i) s.w[i] = c->tab.w[i];
   s.q_src = src;
   s.q_n = qn;
   s.q_dst = dst;
@@ -103,8 +105,10 @@ cpr_status stage(cpr_ctx* c, int mode, const double* src, const double* qn, doub
   return CPR_OK;
 }
 
-cpr_status limit_pass(cpr_ctx* c, double* q, int* flags, int* count, bool device_dt) {
+cpr_status limit_pass(cpr_ctx* c, double* q, int* flags, int* count, bool device_dt,
+                      bool means_ready = false) {
   LimitArgs l{};
+  l.means_ready = means_ready ? 1 : 0;
   l.q = q;
   l.qbar = c->qbar;
   l.flags = flags;
@@ -292,12 +296,14 @@ cpr_status cpr_rk3_step(cpr_ctx* ctx, double* q, double dt, int32_t apply_limite
   }
   cpr_status st;
   const bool lim = apply_limiter != 0;
-  if ((st = stage(ctx, kStageRK, q, nullptr, ctx->q1, nullptr, 0.0, 1.0, dt, ddt)) != CPR_OK) return st;
-  if (lim && (st = limit_pass(ctx, ctx->q1, nullptr, nullptr, ddt)) != CPR_OK) return st;
-  if ((st = stage(ctx, kStageRK, ctx->q1, q, ctx->q2, nullptr, 0.75, 0.25, dt, ddt)) != CPR_OK) return st;
-  if (lim && (st = limit_pass(ctx, ctx->q2, nullptr, nullptr, ddt)) != CPR_OK) return st;
-  if ((st = stage(ctx, kStageRK, ctx->q2, q, q, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, ddt)) != CPR_OK) return st;
-  if (lim && (st = limit_pass(ctx, q, nullptr, nullptr, ddt)) != CPR_OK) return st;
+  // with the limiter, each stage kernel also writes the element means of its
+  // output, which the limiter pass after it then uses
+  if ((st = stage(ctx, kStageRK, q, nullptr, ctx->q1, nullptr, 0.0, 1.0, dt, ddt, lim)) != CPR_OK) return st;
+  if (lim && (st = limit_pass(ctx, ctx->q1, nullptr, nullptr, ddt, true)) != CPR_OK) return st;
+  if ((st = stage(ctx, kStageRK, ctx->q1, q, ctx->q2, nullptr, 0.75, 0.25, dt, ddt, lim)) != CPR_OK) return st;
+  if (lim && (st = limit_pass(ctx, ctx->q2, nullptr, nullptr, ddt, true)) != CPR_OK) return st;
+  if ((st = stage(ctx, kStageRK, ctx->q2, q, q, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, ddt, lim)) != CPR_OK) return st;
+  if (lim && (st = limit_pass(ctx, q, nullptr, nullptr, ddt, true)) != CPR_OK) return st;
   return CPR_OK;
 }
 

@@ -219,7 +219,7 @@ static hipError_t launch_limit_t(const Geometry& g, const Tables1D& T, const Lim
   const WTab<P + 1> w = make_wtab<P + 1>(T);
   const int ne = g.nx * g.ny;
   const dim3 grid((ne + 255) / 256), block(256);
-  hipLaunchKernelGGL((means_kernel<P>), grid, block, 0, s, g, w, a);
+  if (!a.means_ready) hipLaunchKernelGGL((means_kernel<P>), grid, block, 0, s, g, w, a);
   hipLaunchKernelGGL((limit_kernel<P>), grid, block, 0, s, g, w, a);
   return hipGetLastError();
 }

@@ -58,6 +58,8 @@ struct StageArgs {
   const int* skip;       // when non-null and *skip != 0, the kernel does nothing
   int* err;              // set to 1 on a non-physical state
   int vec;               // every state pointer is 16-byte aligned
+  double* qbar;          // when non-null (RK mode): element means of q_dst, 4 * ny * nx
+  double w[kMaxP + 1];   // quadrature weights for those means
 };
 
 enum { kStageRK = 0, kStageResidual = 1 };
@@ -90,6 +92,7 @@ struct LimitArgs {
   double tvb_m;
   const int* skip;  // nullable
   int* err;
+  int means_ready;  // qbar already holds the means of q (written by the stage kernel)
 };
 hipError_t launch_limit(int P, const Geometry& g, const Tables1D& T, const LimitArgs& a,
                         hipStream_t s);

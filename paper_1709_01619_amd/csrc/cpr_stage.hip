@@ -37,7 +37,10 @@
 //  D  row sweep the same way; this tile's q_n loads are issued, then the two
 //     parts are summed and the RK combination b (q_src + dt R) is formed in
 //     float64 and parked in LDS;
-//  E  coalesced epilogue q_dst = a q_n + (parked value).
+//  E  coalesced epilogue q_dst = a q_n + (parked value). When the limiter
+//     follows the stage, the output also stays in LDS and the element means
+//     the limiter needs are formed from it, which saves the limiter its own
+//     pass over the state.
 // Each line is held in registers only during its own sweep, which keeps the
 // register peak low enough for several workgroups per CU. Each
 // tile-boundary face flux is computed by both tiles that share it from
@@ -397,7 +400,7 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       const int sg = TC::run(wv, u);
       const int cy = sg & 7, k = sg >> 3;
       const bool ok = sg < 4 * kTile && cy < nay;
-      const double* img = qs + k * VS + cy * kTile * S;
+      double* img = qs + k * VS + cy * kTile * S;
 #pragma unroll
       for (int it = 0; it < TC::NIT2; ++it) {
         const int f = 2 * (it * 64 + lane);
@@ -405,6 +408,10 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
           const double a0 = img[tc.loff2[it]], a1 = img[tc.loff2b[it]];
           vn[u][it].x = need_qn ? fma(A.a, vn[u][it].x, a0) : a0;
           vn[u][it].y = need_qn ? fma(A.a, vn[u][it].y, a1) : a1;
+          if (A.qbar != nullptr) {  // the output stays in LDS for its element means
+            img[tc.loff2[it]] = vn[u][it].x;
+            img[tc.loff2b[it]] = vn[u][it].y;
+          }
         }
       }
     }
@@ -451,13 +458,14 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       const int sg = TC::run(wv, u);
       const int cy = sg & 7, k = sg >> 3;
       const bool ok = sg < 4 * kTile && cy < nay;
-      const double* img = qs + k * VS + cy * kTile * S;
+      double* img = qs + k * VS + cy * kTile * S;
 #pragma unroll
       for (int it = 0; it < TC::NIT; ++it) {
         const int f = it * 64 + lane;
         if (ok && f < seg_len) {
           const double v = img[tc.loff[it]];
           vn[u][it] = need_qn ? fma(A.a, vn[u][it], v) : v;
+          if (A.qbar != nullptr) img[tc.loff[it]] = vn[u][it];
         }
       }
     }
@@ -480,6 +488,28 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
           else
             static_cast<R*>(A.r_out)[gb + f] = (R)vn[u][it];
         }
+      }
+    }
+  }
+
+  // element means of the output for the limiter pass that follows: the
+  // (i,j) and (j,i) terms are added as a pair first, in the same order as
+  // the limiter's own means kernel, so the two give the same bits
+  if (MODE == kStageRK && A.qbar != nullptr) {
+    __syncthreads();
+    const int ne = G.nx * G.ny;
+    for (int t = tid; t < 4 * 64; t += NT) {
+      const int k = t >> 6, e = t & 63, cx = e & 7, cy = e >> 3;
+      if (cx < nax && cy < nay) {
+        const double* v = qs + k * VS + e * S;
+        double sm = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) {
+          sm = fma(A.w[j] * A.w[j], v[j * N1 + j], sm);
+#pragma unroll
+          for (int i = j + 1; i < N1; ++i) sm = fma(A.w[i] * A.w[j], v[j * N1 + i] + v[i * N1 + j], sm);
+        }
+        A.qbar[k * ne + (J0 + cy) * G.nx + I0 + cx] = 0.25 * sm;
       }
     }
   }
