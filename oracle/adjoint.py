@@ -1,9 +1,10 @@
 """Hand-written discrete adjoint of the CPR residual and of one SSP-RK3 step
 (oracle, NumPy FP64).
 
-residual_vjp(q, v) returns (dR/dq)^T v for the residual of oracle.cpr,
-transposing each of its operations in reverse order: flux evaluation,
-extrapolation to the faces, the Rusanov flux (including the derivative of
+residual_vjp(q, v) returns (dR/dq)^T v for the residual of oracle.cpr (all
+three schemes), transposing each of its operations in reverse order: flux
+evaluation (or, for the chain rule, the Jacobian-vector products and their
+second derivatives), extrapolation to the faces, the Rusanov flux (including the derivative of
 its wave-speed bound lam = max(|u_n|+c); sign(0) = +1 for |u_n|), the
 correction lift and the derivative contraction. Where the two one-sided
 speeds tie, |lamL - lamR| <= 1e-12 max(lamL, lamR), max is not
@@ -67,22 +68,42 @@ def rusanov_vjp(qL, qR, s, gamma, axis):
     return cL, cR
 
 
+def _hess_apply(q, a, d, gamma, axis, h=1e-30):
+    """d/dq [a . A(q) d] at every point (A = B for axis 1): the second
+    derivatives of the flux contracted with a and d, by complex-step
+    differentiation of the flux Jacobian along each conserved variable
+    (exact to rounding for these rational formulas)."""
+    out = np.zeros(q.shape)
+    for m in range(4):
+        qc = q.astype(complex)
+        qc[m] = qc[m] + 1j * h
+        A = euler.flux_jacobian(qc, gamma, axis)
+        out[m] = np.imag(np.einsum("ab...,a...,b...->...", A, a, d)) / h
+    return out
+
+
 def residual_vjp(q, v, grid: Grid):
-    """(dR/dq)^T v for R = oracle.cpr.residual; same shape as q. Schemes
-    with the derivative of the flux interpolant only (Gauss-Legendre and
-    Gauss-Lobatto points): the chain rule's transpose would need the second
-    derivatives of the flux."""
-    if grid.scheme == cpr.GLL_CHAIN:
-        raise NotImplementedError("the chain-rule scheme has no transpose here")
+    """(dR/dq)^T v for R = oracle.cpr.residual; same shape as q. For the
+    chain-rule scheme the divergence A(q_i)(Dq)_i transposes into
+    D^T (A(q)^T a) (through Dq) plus the second-derivative term
+    d/dq [a . A(q) (Dq)] at each point (through A); the face terms are those
+    of the other schemes with the flux interpolant's face values."""
+    chain = grid.scheme == cpr.GLL_CHAIN
     T = grid.tables()
     g = grid.gamma
     out = np.zeros_like(q)
 
     # ---------------- x direction ----------------
     a = -(2.0 / grid.dx) * v
-    cot_f = np.einsum("kJIji,il->kJIjl", a, T.D)
     sW = a @ T.gLp                          # cotangent of F_W, (4, ny, nx, n1_j)
     sE = a @ T.gRp
+    if chain:
+        dq = np.einsum("il,kJIjl->kJIji", T.D, q)
+        out += np.einsum("kJIji,il->kJIjl", _jac_t_apply(q, a, g, 0), T.D)
+        out += _hess_apply(q, a, dq, g, 0)
+        cot_f = np.zeros_like(q)
+    else:
+        cot_f = np.einsum("kJIji,il->kJIjl", a, T.D)
     cot_f -= sW[..., None] * T.em + sE[..., None] * T.ep
     # face fluxes 0..nx
     nx = grid.nx
@@ -104,9 +125,15 @@ def residual_vjp(q, v, grid: Grid):
 
     # ---------------- y direction ----------------
     b = -(2.0 / grid.dy) * v
-    cot_g = np.einsum("kJIji,jl->kJIli", b, T.D)
     sS = np.einsum("kJIji,j->kJIi", b, T.gLp)
     sN = np.einsum("kJIji,j->kJIi", b, T.gRp)
+    if chain:
+        dq = np.einsum("jl,kJIli->kJIji", T.D, q)
+        out += np.einsum("kJIji,jl->kJIli", _jac_t_apply(q, b, g, 1), T.D)
+        out += _hess_apply(q, b, dq, g, 1)
+        cot_g = np.zeros_like(q)
+    else:
+        cot_g = np.einsum("kJIji,jl->kJIli", b, T.D)
     cot_g -= sS[..., None, :] * T.em[:, None] + sN[..., None, :] * T.ep[:, None]
     ny = grid.ny
     cot_G = np.zeros((4, ny + 1, grid.nx, grid.n1), dtype=q.dtype)

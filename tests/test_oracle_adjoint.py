@@ -38,7 +38,7 @@ def test_rusanov_vjp_dot_product(axis):
 
 @pytest.mark.parametrize("P", [1, 2, 3, 4])
 @pytest.mark.parametrize("bc", ["periodic", "transmissive"])
-@pytest.mark.parametrize("scheme", [cpr.GL_LP, cpr.GLL_LP])
+@pytest.mark.parametrize("scheme", [cpr.GL_LP, cpr.GLL_LP, cpr.GLL_CHAIN])
 def test_residual_vjp_dot_product(P, bc, scheme):
     g = cpr.Grid(P=P, nx=3, ny=4, x0=0.0, x1=1.5, y0=0.0, y1=2.0, bc=bc, scheme=scheme)
     q = inputs.random_state((g.ny, g.nx, g.n1, g.n1), seed=60 + P)
@@ -68,8 +68,9 @@ def test_residual_vjp_full_matrix_small():
     np.testing.assert_allclose(J_rows, J_cols, rtol=1e-12, atol=1e-12 * np.abs(J_cols).max())
 
 
-def test_rk3_adjoint_step_dot_product():
-    g = cpr.Grid(P=2, nx=3, ny=3, x1=3.0, y1=3.0)
+@pytest.mark.parametrize("scheme", [cpr.GL_LP, cpr.GLL_LP, cpr.GLL_CHAIN])
+def test_rk3_adjoint_step_dot_product(scheme):
+    g = cpr.Grid(P=2, nx=3, ny=3, x1=3.0, y1=3.0, scheme=scheme)
     q = inputs.random_state((3, 3, 3, 3), seed=90)
     dt = 0.05
     rng = np.random.default_rng(91)
@@ -104,8 +105,21 @@ def test_gradient_matches_central_differences():
         assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
 
 
-def test_chain_rule_scheme_has_no_transpose():
-    g = cpr.Grid(P=2, nx=2, ny=2, scheme=cpr.GLL_CHAIN)
-    q = inputs.random_state((2, 2, 3, 3), seed=1)
-    with pytest.raises(NotImplementedError):
-        adjoint.residual_vjp(q, q, g)
+@pytest.mark.parametrize("P", [1, 3])
+def test_chain_rule_vjp_full_matrix(P):
+    """Every column of the chain-rule residual's Jacobian on a 2x2 mesh by
+    complex step, against the transpose applied to unit vectors."""
+    g = cpr.Grid(P=P, nx=2, ny=2, x1=1.0, y1=0.8, scheme=cpr.GLL_CHAIN)
+    q = inputs.random_state((2, 2, P + 1, P + 1), seed=90 + P)
+    n = q.size
+    J = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        J[:, c] = _cs_jvp(lambda z: cpr.residual(z, g), q, e.reshape(q.shape)).ravel()
+    JT = np.zeros((n, n))
+    for r in range(n):
+        e = np.zeros(n)
+        e[r] = 1.0
+        JT[r, :] = adjoint.residual_vjp(q, e.reshape(q.shape), g).ravel()
+    assert np.max(np.abs(JT - J)) <= 1e-12 * np.max(np.abs(J))
