@@ -153,7 +153,10 @@ cpr_status cpr_limit(cpr_ctx* ctx, double* q, int32_t* flags, int32_t* n_trouble
  * sides' gradients is used). In CPR_FP32_BULK contexts the transpose is
  * evaluated in float32 (as the residual is) and its two sweep parts are
  * summed in float64. q, v, out: device float64 states; out must not alias
- * q or v. CPR_EUNSUPPORTED for a CPR_SCHEME_GLL_CHAIN context. */
+ * q or v. For CPR_SCHEME_GLL_CHAIN the divergence A(q_i) (Dq)_i transposes
+ * into sum_i D_il A(q_i)^T a_i plus the flux's second derivatives
+ * d/dq [a_l . A(q) (Dq)_l] at q_l (a = -(2/h) v), evaluated together on
+ * dual numbers q_l + eps (Dq)_l. */
 cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, double* out);
 
 /* Discrete adjoint of one unlimited SSP-RK3 step of size dt > 0 from q_n:
@@ -163,8 +166,7 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
  * All pointers device float64 states; lam_n may alias lam_np1. In
  * CPR_FP32_BULK contexts the stage states are recomputed with the float32
  * residual and the J^T products are float32 (cpr_residual_vjp); the lam
- * combinations are float64. CPR_EUNSUPPORTED on a context with a limiter
- * or with CPR_SCHEME_GLL_CHAIN. */
+ * combinations are float64. CPR_EUNSUPPORTED on a context with a limiter. */
 cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt,
                             const double* lam_np1, double* lam_n);
 

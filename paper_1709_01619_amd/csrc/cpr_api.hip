@@ -330,10 +330,6 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
     set_err(ctx, "cpr_residual_vjp: out must not alias q or v");
     return CPR_EINVAL;
   }
-  if (ctx->cfg.scheme == CPR_SCHEME_GLL_CHAIN) {
-    set_err(ctx, "cpr_residual_vjp: the chain-rule scheme is not differentiated");
-    return CPR_EUNSUPPORTED;
-  }
   return vjp(ctx, q, v, nullptr, nullptr, out, 0.0, 1.0, 0.0, 0.0);
 }
 
@@ -342,10 +338,6 @@ namespace {
 cpr_status adjoint_checks(cpr_ctx* ctx, const char* who) {
   if (ctx->cfg.limiter != CPR_LIM_NONE) {
     set_err(ctx, "%s: the limiter is not differentiated", who);
-    return CPR_EUNSUPPORTED;
-  }
-  if (ctx->cfg.scheme == CPR_SCHEME_GLL_CHAIN) {
-    set_err(ctx, "%s: the chain-rule scheme is not differentiated", who);
     return CPR_EUNSUPPORTED;
   }
   return CPR_OK;

@@ -25,20 +25,48 @@
 
 namespace cpr {
 
-// (dF_AX/dq)^T s at state q.
-template <int AX, typename R>
-__device__ __forceinline__ void flux_jac_t(const R q[4], R gam, const R s[4], R out[4]) {
+// A number with a first-order perturbation, v + d eps (eps^2 = 0): evaluating
+// a function on it gives the function's value and its derivative along d.
+template <typename R>
+struct Dual {
+  R v, d;
+};
+template <typename R>
+__device__ __forceinline__ Dual<R> operator+(Dual<R> a, Dual<R> b) { return {a.v + b.v, a.d + b.d}; }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator-(Dual<R> a, Dual<R> b) { return {a.v - b.v, a.d - b.d}; }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator*(Dual<R> a, Dual<R> b) {
+  return {a.v * b.v, a.v * b.d + a.d * b.v};
+}
+template <typename R>
+__device__ __forceinline__ Dual<R> operator*(R a, Dual<R> b) { return {a * b.v, a * b.d}; }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator+(R a, Dual<R> b) { return {a + b.v, b.d}; }
+template <typename R>
+__device__ __forceinline__ Dual<R> operator-(Dual<R> a) { return {-a.v, -a.d}; }
+template <typename R>
+__device__ __forceinline__ Dual<R> recip(Dual<R> x) {
+  const R r = recip(x.v);
+  return {r, -(x.d * r) * r};
+}
+
+// (dF_AX/dq)^T s at state q. T is the compute type R, or Dual<R> for the
+// derivative of the product along a direction of q (the flux's second
+// derivatives contracted with s and that direction).
+template <int AX, typename R, typename T = R>
+__device__ __forceinline__ void flux_jac_t(const T q[4], R gam, const T s[4], T out[4]) {
   constexpr int n = 1 + AX, t = 2 - AX;
-  const R ir = recip(q[0]);
-  const R un = q[n] * ir, ut = q[t] * ir;
+  const T ir = recip(q[0]);
+  const T un = q[n] * ir, ut = q[t] * ir;
   const R gm1 = gam - R(1);
-  const R ke = R(0.5) * (un * un + ut * ut);
-  const R p = gm1 * (q[3] - q[0] * ke);
-  const R H = (q[3] + p) * ir;
-  const R phi = gm1 * ke;
+  const T ke = R(0.5) * (un * un + ut * ut);
+  const T p = gm1 * (q[3] - q[0] * ke);
+  const T H = (q[3] + p) * ir;
+  const T phi = gm1 * ke;
   out[0] = (phi - un * un) * s[n] - un * ut * s[t] + un * (phi - H) * s[3];
   out[n] = s[0] + (R(3) - gam) * un * s[n] + ut * s[t] + (H - gm1 * un * un) * s[3];
-  out[t] = -gm1 * ut * s[n] + un * s[t] - gm1 * un * ut * s[3];
+  out[t] = (-gm1) * ut * s[n] + un * s[t] - gm1 * un * ut * s[3];
   out[3] = gm1 * s[n] + gam * un * s[3];
 }
 
@@ -133,7 +161,63 @@ __device__ __forceinline__ void line_adj_finish(const R q[4][N1], const LineAdj<
   }
 }
 
-template <int P, typename R>
+// cot q on the line for the chain-rule scheme (Gauss-Lobatto points, the
+// paper's CPR). Its divergence A(q_i) d_i, d_i = sum_m D_im q_m, transposes
+// into sum_i D_il A(q_i)^T a_i (through d) plus d/dq [a_l . A(q) d_l] at q_l
+// (through A), both from one evaluation of A(q)^T a on q_l + eps d_l; the
+// flux interpolant's face values are the end points' fluxes, so the sigma
+// terms and the face-state cotangents act at the two end points only.
+template <int N1, int AX, typename R>
+__device__ __forceinline__ void line_adj_finish_chain(const R q[4][N1], const LineAdj<N1, AX, R>& L,
+                                                      const R clo[4], const R chi[4],
+                                                      const KTab<R, N1>& T, R gam,
+                                                      R out[4][N1]) {
+  R w[4][N1];
+#pragma unroll
+  for (int l = 0; l < N1; ++l) {
+    Dual<R> qd[4], sd[4], od[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      qd[k] = {q[k][l], dot_n<N1>([&](int m) { return T.D(l, m); }, q[k])};
+      sd[k] = {L.a[k][l], R(0)};
+    }
+    flux_jac_t<AX, R, Dual<R>>(qd, gam, sd, od);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w[k][l] = od[k].v;    // A(q_l)^T a_l
+      out[k][l] = od[k].d;  // d/dq [a_l . A(q) d_l]
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < N1; ++l)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      R acc = out[k][l];
+#pragma unroll
+      for (int i = 0; i < N1; ++i) acc += T.D(i, l) * w[k][i];
+      out[k][l] = acc;
+    }
+  // end points: the interpolant's face values f(q_0), f(q_N) and the face states
+  R ms[4], jt[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ms[k] = -L.slo[k];
+  {
+    const R q0[4] = {q[0][0], q[1][0], q[2][0], q[3][0]};
+    flux_jac_t<AX, R>(q0, gam, ms, jt);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k][0] += jt[k] + clo[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) ms[k] = -L.shi[k];
+  {
+    const R qn[4] = {q[0][N1 - 1], q[1][N1 - 1], q[2][N1 - 1], q[3][N1 - 1]};
+    flux_jac_t<AX, R>(qn, gam, ms, jt);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k][N1 - 1] += jt[k] + chi[k];
+  }
+}
+
+template <int P, typename R, bool CHAIN>
 __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P + 1> T, VjpArgs A) {
   constexpr int N1 = P + 1;
   constexpr int NSP = N1 * N1;
@@ -366,7 +450,10 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 #pragma unroll
       for (int k = 0; k < 4; ++k) chi[k] = hC[3][cxY][wv][k];
     }
-    line_adj_finish<N1, 1>(qcol, L, clo, chi, T, gam, oc);
+    if constexpr (CHAIN)
+      line_adj_finish_chain<N1, 1>(qcol, L, clo, chi, T, gam, oc);
+    else
+      line_adj_finish<N1, 1>(qcol, L, clo, chi, T, gam, oc);
     if (actY) bad = bad || b2;
   }
 
@@ -418,7 +505,10 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 #pragma unroll
       for (int k = 0; k < 4; ++k) chi[k] = hC[1][cyX][wv][k];
     }
-    line_adj_finish<N1, 0>(qrow, L, clo, chi, T, gam, orow);
+    if constexpr (CHAIN)
+      line_adj_finish_chain<N1, 0>(qrow, L, clo, chi, T, gam, orow);
+    else
+      line_adj_finish<N1, 0>(qrow, L, clo, chi, T, gam, orow);
     if (actX) bad = bad || b2;
   }
   __syncthreads();
@@ -543,22 +633,27 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 
 template <int P, typename R>
 static hipError_t launch_vjp_t(const Geometry& g, const Tables1D& T, const VjpArgs& a,
-                               hipStream_t s) {
+                               bool chain, hipStream_t s) {
   const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T, g);
-  hipLaunchKernelGGL((vjp_kernel<P, R>), dim3(g.ntx * g.nty), dim3(64 * (P + 1)), 0, s, g, kt, a);
+  const dim3 grid(g.ntx * g.nty), block(64 * (P + 1));
+  if (chain)
+    hipLaunchKernelGGL((vjp_kernel<P, R, true>), grid, block, 0, s, g, kt, a);
+  else
+    hipLaunchKernelGGL((vjp_kernel<P, R, false>), grid, block, 0, s, g, kt, a);
   return hipGetLastError();
 }
 
 hipError_t launch_vjp(int P, bool fp32, int scheme, const Geometry& g, const Tables1D& T,
                       const VjpArgs& a, hipStream_t s) {
-  // the transpose of the flux-interpolant schemes only (either point set:
-  // the face rows are used as given)
-  if (scheme == kSchemeGllChain || T.points != scheme_points(scheme)) return hipErrorInvalidValue;
+  // the chain-rule transpose takes the face values at the end points, so it
+  // needs the Gauss-Lobatto tables
+  if (T.points != scheme_points(scheme)) return hipErrorInvalidValue;
+  const bool c = scheme == kSchemeGllChain;
   switch (P) {
-    case 1: return fp32 ? launch_vjp_t<1, float>(g, T, a, s) : launch_vjp_t<1, double>(g, T, a, s);
-    case 2: return fp32 ? launch_vjp_t<2, float>(g, T, a, s) : launch_vjp_t<2, double>(g, T, a, s);
-    case 3: return fp32 ? launch_vjp_t<3, float>(g, T, a, s) : launch_vjp_t<3, double>(g, T, a, s);
-    case 4: return fp32 ? launch_vjp_t<4, float>(g, T, a, s) : launch_vjp_t<4, double>(g, T, a, s);
+    case 1: return fp32 ? launch_vjp_t<1, float>(g, T, a, c, s) : launch_vjp_t<1, double>(g, T, a, c, s);
+    case 2: return fp32 ? launch_vjp_t<2, float>(g, T, a, c, s) : launch_vjp_t<2, double>(g, T, a, c, s);
+    case 3: return fp32 ? launch_vjp_t<3, float>(g, T, a, c, s) : launch_vjp_t<3, double>(g, T, a, c, s);
+    case 4: return fp32 ? launch_vjp_t<4, float>(g, T, a, c, s) : launch_vjp_t<4, double>(g, T, a, c, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import inputs
-from oracle import cpr, euler, limiter, tables
+from oracle import adjoint, cpr, euler, limiter, tables
 from tests.golden_data import PAPER_COLUMN, PAPER_L2_RTOL, paper_vortex_l2
 from tests.gpu_util import dev, host, make_solver, rel_err, say, torch
 from tests.test_gpu_limiter_adjoint import _blurred_riemann, _margins
@@ -252,16 +252,105 @@ def test_chain_limited_riemann_steps_match_oracle():
     assert np.max(np.abs(_transpose(qg) - qg)) <= 1e-12
 
 
-def test_chain_adjoint_unsupported():
-    from paper_1709_01619_amd import _lib
-    g = cpr.Grid(P=2, nx=4, ny=4, scheme=CH)
-    q = inputs.random_state((4, 4, 3, 3), seed=5)
-    say("chain adjoint rejected")
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("mesh", [(1, 1), (3, 5), (9, 8), (13, 11)], ids=lambda m: f"{m[0]}x{m[1]}")
+def test_chain_residual_vjp_matches_oracle(mesh, P, bc):
+    """Transpose of the chain-rule residual: D^T applied to A(q)^T a, the
+    flux's second derivatives contracted with a and Dq (dual numbers in the
+    kernel, complex-step differentiation in the oracle) and the end-point
+    face terms; both in float64, 1e-12 of the largest entry."""
+    nx, ny = mesh
+    g = cpr.Grid(P=P, nx=nx, ny=ny, x0=0.0, x1=2.0, y0=0.0, y1=1.5, bc=bc, scheme=CH)
+    q = inputs.random_state((ny, nx, P + 1, P + 1), seed=6100 + P + nx)
+    v = np.random.default_rng(6200 + P).standard_normal(g.shape)
+    say("chain vjp", P, nx, ny, bc)
+    ref = adjoint.residual_vjp(q, v, g)
+    out = host(make_solver(g).residual_vjp(dev(q), dev(v)))
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _chain_vjp_fp32_scale(q, v, g):
+    """Size of the terms the float32 chain-rule transpose is formed from:
+    (2/h) max|v| [(||D||_1 + 2||g'||_inf)(max||A(q)||_inf + 2 lam)
+    + max_m ||dA/dq_m||_1 max|Dq|], the second derivatives of the flux
+    taken by complex step."""
+    T = tables.get(g.P, "gll")
+    normD = np.max(np.sum(np.abs(T.D), axis=0))
+    normg = max(np.max(np.abs(T.gLp)), np.max(np.abs(T.gRp)))
+    A, H = 0.0, 0.0
+    for ax in (0, 1):
+        J = euler.flux_jacobian(q, g.gamma, ax)
+        A = max(A, np.max(np.sum(np.abs(J), axis=0)), np.max(np.sum(np.abs(J), axis=1)))
+        for m in range(4):
+            qc = q.astype(complex)
+            qc[m] = qc[m] + 1e-30j
+            dJ = np.imag(euler.flux_jacobian(qc, g.gamma, ax)) / 1e-30
+            H = max(H, np.max(np.sum(np.abs(dJ), axis=(0, 1))))
+    dq = max(np.max(np.abs(np.einsum("il,kJIjl->kJIji", T.D, q))),
+             np.max(np.abs(np.einsum("jl,kJIli->kJIji", T.D, q))))
+    lam = np.max(euler.max_wave_speed(q, g.gamma))
+    return (2.0 / min(g.dx, g.dy) * np.max(np.abs(v))
+            * ((normD + 2 * normg) * (A + 2 * lam) + H * dq))
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_chain_residual_vjp_fp32_bulk(P, bc):
+    """FP32-bulk chain-rule transpose against the float64 oracle: 64 units
+    of 2^-24 on the scale of the terms it is formed from."""
+    g = cpr.Grid(P=P, nx=9, ny=8, x0=0.0, x1=2.0, y0=0.0, y1=1.5, bc=bc, scheme=CH)
+    q = inputs.random_state((8, 9, P + 1, P + 1), seed=6300 + P)
+    v = np.random.default_rng(6400 + P).standard_normal(g.shape)
+    say("chain vjp fp32_bulk", P, bc)
+    ref = adjoint.residual_vjp(q, v, g)
+    out = host(make_solver(g, precision="fp32_bulk").residual_vjp(dev(q), dev(v)))
+    err = np.max(np.abs(out - ref))
+    scale = _chain_vjp_fp32_scale(q, v, g)
+    print(f"chain fp32_bulk vjp P={P} {bc}: max err {err:.3e} = "
+          f"{err / np.max(np.abs(ref)):.2e} of max|ref|, bound {64 * 2.0 ** -24 * scale:.3e}")
+    assert err <= 64 * 2.0 ** -24 * scale
+
+
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+def test_chain_adjoint_step_matches_oracle(P):
+    g = cpr.Grid(P=P, nx=10, ny=9, scheme=CH)
+    x, y = g.coords()
+    q = inputs.Vortex().conserved(x, y)
+    lam = np.random.default_rng(6500 + P).standard_normal(g.shape)
+    say("chain adjoint step", P)
+    ref = adjoint.rk3_adjoint_step(q, 0.01, lam, g)
+    out = host(make_solver(g).adjoint_step(dev(q), 0.01, dev(lam)))
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_chain_rollout_gradient_matches_oracle_and_fd():
+    """Gradient of the density misfit after 8 chain-rule steps of the
+    perturbed vortex (P=2, 8x8) through Rollout: equal to the oracle's
+    adjoint gradient, and to central differences of the oracle's misfit
+    along four seeded directions."""
+    from paper_1709_01619_amd import Rollout
+    g = cpr.Grid(P=2, nx=8, ny=8, scheme=CH)
+    x, y = g.coords()
+    V = inputs.Vortex()
+    q0 = V.conserved(x, y)
+    q0[0] += inputs.gaussian_perturbation(q0[0].shape, 1e-3, 0)
+    dt, n = 0.02, 8
+    rho_ex = V.conserved(x, y, dt * n)[0]
+    say("chain rollout gradient")
+    J_o, g_o = adjoint.gradient(q0, dt, n, g, rho_ex)
     s = make_solver(g)
-    qd = dev(q)
-    with pytest.raises(_lib.CprError) as ei:
-        s.residual_vjp(qd, dev(q))
-    assert ei.value.status == _lib.CPR_EUNSUPPORTED
-    with pytest.raises(_lib.CprError) as ei:
-        s.adjoint_step(qd, 0.01, dev(q))
-    assert ei.value.status == _lib.CPR_EUNSUPPORTED
+    W = s.quad_weights()
+    q0d = dev(q0).requires_grad_(True)
+    qT = Rollout.apply(q0d, s, dt, n, 3)
+    J = 0.5 * ((qT[0] - dev(rho_ex)) ** 2 * W).sum()
+    J.backward()
+    gg = host(q0d.grad)
+    assert abs(J.item() - J_o) <= 1e-12 * J_o
+    assert np.max(np.abs(gg - g_o)) <= 1e-11 * np.max(np.abs(g_o))
+    for d in inputs.random_directions(g.shape, [1100, 1101, 1102, 1103]):
+        h = 1e-6 * np.max(np.abs(q0)) / np.max(np.abs(d))
+        Jp = adjoint.misfit(cpr.run(q0 + h * d, g, dt, n), rho_ex, g)
+        Jm = adjoint.misfit(cpr.run(q0 - h * d, g, dt, n), rho_ex, g)
+        ad = float(np.sum(gg * d))
+        assert abs((Jp - Jm) / (2 * h) - ad) <= 1e-6 * abs(ad)

@@ -290,7 +290,7 @@ def test_residual_vjp_misaligned_matches_aligned(nx, P, prec):
 
 
 @pytest.mark.parametrize("P", [2, 3])
-@pytest.mark.parametrize("scheme", ["gl_lp", "gll_lp"])
+@pytest.mark.parametrize("scheme", ["gl_lp", "gll_chain", "gll_lp"])
 def test_step_and_adjoint_with_stage_states(P, scheme):
     """cpr_rk3_step_stages returns the oracle's stage states and the same
     step as cpr_rk3_step; cpr_adjoint_step_stages given them equals
