@@ -473,6 +473,24 @@ def profile_legs(a):
             q = vortex_state(s)
             ms = time_steps(s, q, 1e-4, a.steps, a.warmup)
             print(f"scale P=4 1024^2 {prec}: {ms:.4f} ms/step", flush=True)
+    if "adjoint" in legs:
+        # one checkpoint segment of the P=4 1024^2 adjoint workload (a.steps
+        # steps, checkpoint a.steps) and of the P=3 128^2 one, forward and
+        # backward
+        from paper_1709_01619_amd import Rollout
+        for P, n, dt in ((4, 1024, 1e-4), (3, 128, 1e-3)):
+            for prec in ("fp64", "fp32_bulk"):
+                s = Solver(P, n, n, precision=prec)
+                q0 = vortex_state(s).requires_grad_(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                qT = Rollout.apply(q0, s, dt, a.steps, a.steps)
+                (qT[0] ** 2).sum().backward()
+                torch.cuda.synchronize()
+                print(f"adjoint P={P} {n}^2 {prec}: {a.steps} steps forward + backward in "
+                      f"{time.perf_counter() - t0:.4f} s", flush=True)
+                del s, q0, qT
+                torch.cuda.empty_cache()
     return 0
 
 
@@ -486,7 +504,8 @@ def main(argv=None):
                     help="skip the t=10 error runs, the adjoint and the P=4 legs")
     ap.add_argument("--legs", default="all",
                     help="comma list of legs to run for profiling: main, scale, chain, "
-                         "copy (a 1 GiB device copy that calibrates HBM byte counters); "
+                         "adjoint, copy (a 1 GiB device copy that calibrates HBM byte "
+                         "counters); "
                          "prints a short text report instead of the JSON line")
     a = ap.parse_args(argv)
     if a.legs != "all":

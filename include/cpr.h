@@ -65,7 +65,7 @@
 extern "C" {
 #endif
 
-#define CPR_ABI_VERSION 1
+#define CPR_ABI_VERSION 2
 
 typedef struct cpr_ctx cpr_ctx;
 
@@ -170,13 +170,17 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
 cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt,
                             const double* lam_np1, double* lam_n);
 
-/* One unlimited SSP-RK3 step of size dt > 0 (as cpr_rk3_step with that dt
- * and no limiter) that also hands back its stage states: q1 = qn + dt R(qn),
- * q2 = 3/4 qn + 1/4 (q1 + dt R(q1)); q advances in place to q(n+1). For
- * adjoint sweeps that keep the states of a checkpoint segment
- * (cpr_adjoint_step_stages), which then need not recompute them. q, q1, q2:
- * distinct device float64 states (CPR_EINVAL otherwise). */
-cpr_status cpr_rk3_step_stages(cpr_ctx* ctx, double* q, double dt, double* q1, double* q2);
+/* One unlimited SSP-RK3 step of size dt > 0 from q_n (as cpr_rk3_step with
+ * that dt and no limiter) that also hands back its stage states:
+ * q1 = qn + dt R(qn), q2 = 3/4 qn + 1/4 (q1 + dt R(q1)), and
+ * q_out = q(n+1) = 1/3 qn + 2/3 (q2 + dt R(q2)). q_out may be q_n (the step
+ * in place); otherwise q_n is left unchanged. For adjoint sweeps that keep
+ * the states of a checkpoint segment (cpr_adjoint_step_stages), which then
+ * need not recompute them, and that chain the steps of the segment without
+ * copies. All pointers device float64 states; q_n, q1 and q2 distinct, and
+ * q_out distinct from q1 and q2 (CPR_EINVAL otherwise). */
+cpr_status cpr_rk3_step_stages(cpr_ctx* ctx, double* q_n, double dt, double* q1, double* q2,
+                               double* q_out);
 
 /* cpr_adjoint_step with the step's stage states q1, q2 supplied (from
  * cpr_rk3_step_stages on q_n and the same dt) instead of recomputed: the

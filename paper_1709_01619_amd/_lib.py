@@ -14,7 +14,7 @@ from ctypes import POINTER, c_double, c_int32, c_int64, c_void_p
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpr.so")
 
-CPR_ABI_VERSION = 1
+CPR_ABI_VERSION = 2
 CPR_OK, CPR_EINVAL, CPR_ENOMEM, CPR_EHIP, CPR_EUNSUPPORTED, CPR_ENONPHYSICAL = 0, -1, -2, -3, -4, -5
 CPR_BC_PERIODIC, CPR_BC_TRANSMISSIVE = 0, 1
 CPR_FP64, CPR_FP32_BULK = 0, 1
@@ -87,7 +87,7 @@ def load(path: str = LIB_PATH):
         "cpr_limit": (c_int32, [c_void_p, c_void_p, c_void_p, P(c_int32)]),
         "cpr_residual_vjp": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
         "cpr_adjoint_step": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
-        "cpr_rk3_step_stages": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
+        "cpr_rk3_step_stages": (c_int32, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
         "cpr_adjoint_step_stages": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double,
                                               c_void_p, c_void_p]),
         "cpr_max_wavespeed": (c_int32, [c_void_p, c_void_p, P(c_double)]),

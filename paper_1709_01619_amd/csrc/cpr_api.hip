@@ -370,17 +370,21 @@ cpr_status cpr_adjoint_step(cpr_ctx* ctx, const double* q_n, double dt, const do
   return adjoint_sweep(ctx, q_n, ctx->q1, ctx->q2, dt, lam_np1, lam_n);
 }
 
-cpr_status cpr_rk3_step_stages(cpr_ctx* ctx, double* q, double dt, double* q1, double* q2) {
-  if (ctx == nullptr || q == nullptr || q1 == nullptr || q2 == nullptr) return CPR_EINVAL;
+cpr_status cpr_rk3_step_stages(cpr_ctx* ctx, double* q_n, double dt, double* q1, double* q2,
+                               double* q_out) {
+  if (ctx == nullptr || q_n == nullptr || q1 == nullptr || q2 == nullptr || q_out == nullptr)
+    return CPR_EINVAL;
   if (!(std::isfinite(dt) && dt > 0.0)) return CPR_EINVAL;
-  if (q1 == q || q2 == q || q1 == q2) {
-    set_err(ctx, "cpr_rk3_step_stages: q, q1 and q2 must be distinct");
+  if (q1 == q_n || q2 == q_n || q1 == q2 || q_out == q1 || q_out == q2) {
+    set_err(ctx, "cpr_rk3_step_stages: q_n, q1 and q2 must be distinct, q_out must not be q1 or q2");
     return CPR_EINVAL;
   }
   cpr_status st;
-  if ((st = stage(ctx, kStageRK, q, nullptr, q1, nullptr, 0.0, 1.0, dt, false)) != CPR_OK) return st;
-  if ((st = stage(ctx, kStageRK, q1, q, q2, nullptr, 0.75, 0.25, dt, false)) != CPR_OK) return st;
-  return stage(ctx, kStageRK, q2, q, q, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, false);
+  if ((st = stage(ctx, kStageRK, q_n, nullptr, q1, nullptr, 0.0, 1.0, dt, false)) != CPR_OK) return st;
+  if ((st = stage(ctx, kStageRK, q1, q_n, q2, nullptr, 0.75, 0.25, dt, false)) != CPR_OK) return st;
+  // out of place the third stage reads q2 and q_n and writes q_out, which
+  // aliases neither (a tile may only overwrite what no other tile reads)
+  return stage(ctx, kStageRK, q2, q_n, q_out, nullptr, 1.0 / 3.0, 2.0 / 3.0, dt, false);
 }
 
 cpr_status cpr_adjoint_step_stages(cpr_ctx* ctx, const double* q_n, const double* q1,

@@ -166,13 +166,17 @@ class Solver:
                                               self._ptr(out, name="lam_n")), "cpr_adjoint_step")
         return out
 
-    def step_stages(self, q, dt, q1, q2):
-        """One unlimited SSP-RK3 step of q in place that also writes its stage
-        states into q1 and q2 (cpr_rk3_step_stages)."""
+    def step_stages(self, q, dt, q1, q2, out=None):
+        """One unlimited SSP-RK3 step from q that also writes its stage
+        states into q1 and q2 (cpr_rk3_step_stages); q(n+1) goes to out, by
+        default q itself (in place)."""
+        out = q if out is None else out
         self._enter()
         self._check(self.lib.cpr_rk3_step_stages(self._ctx, self._ptr(q, name="q"), float(dt),
                                                  self._ptr(q1, name="q1"),
-                                                 self._ptr(q2, name="q2")), "cpr_rk3_step_stages")
+                                                 self._ptr(q2, name="q2"),
+                                                 self._ptr(out, name="out")),
+                    "cpr_rk3_step_stages")
 
     def adjoint_step_stages(self, q_n, q1, q2, dt, lam_np1, out=None):
         """cpr_adjoint_step_stages: the adjoint step with the stage states
@@ -302,8 +306,7 @@ def _rollout_fn():
                 for i in range(s1 - s0):
                     last = i == s1 - s0 - 1
                     z = nxt if last else seg[i + 1, 0]   # q of the next step (unused after the last)
-                    z.copy_(seg[i, 0])
-                    solver.step_stages(z, dt, seg[i, 1], seg[i, 2])
+                    solver.step_stages(seg[i, 0], dt, seg[i, 1], seg[i, 2], out=z)
                 for i in range(s1 - s0 - 1, -1, -1):
                     solver.adjoint_step_stages(seg[i, 0], seg[i, 1], seg[i, 2], dt, lam, out=lam)
             return lam, None, None, None, None

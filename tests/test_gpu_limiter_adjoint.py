@@ -293,8 +293,8 @@ def test_residual_vjp_misaligned_matches_aligned(nx, P, prec):
 @pytest.mark.parametrize("scheme", ["gl_lp", "gll_chain", "gll_lp"])
 def test_step_and_adjoint_with_stage_states(P, scheme):
     """cpr_rk3_step_stages returns the oracle's stage states and the same
-    step as cpr_rk3_step; cpr_adjoint_step_stages given them equals
-    cpr_adjoint_step bit for bit; aliasing is rejected."""
+    step as cpr_rk3_step, in place or out of place; cpr_adjoint_step_stages
+    given them equals cpr_adjoint_step bit for bit; aliasing is rejected."""
     from paper_1709_01619_amd import _lib
     t = torch()
     g = cpr.Grid(P=P, nx=10, ny=9, scheme=scheme)
@@ -307,6 +307,10 @@ def test_step_and_adjoint_with_stage_states(P, scheme):
     qa, qb = dev(q), dev(q)
     q1, q2 = t.empty_like(qa), t.empty_like(qa)
     s.step(qa, dt)
+    q0 = dev(q)
+    qo = t.empty_like(qa)
+    s.step_stages(q0, dt, q1, q2, out=qo)          # out of place: q_n is kept
+    assert t.equal(qo, qa) and t.equal(q0, dev(q))
     s.step_stages(qb, dt, q1, q2)
     assert t.equal(qa, qb)
     _, o1, o2, _ = cpr.rk3_stages(q, dt, g)
@@ -319,6 +323,9 @@ def test_step_and_adjoint_with_stage_states(P, scheme):
     assert np.array_equal(host(ld), ref)
     with pytest.raises(_lib.CprError) as ei:
         s.step_stages(qb, dt, q1, q1)
+    assert ei.value.status == _lib.CPR_EINVAL
+    with pytest.raises(_lib.CprError) as ei:
+        s.step_stages(qb, dt, q1, q2, out=q2)
     assert ei.value.status == _lib.CPR_EINVAL
     with pytest.raises(_lib.CprError) as ei:
         s.adjoint_step_stages(qb, q1, q2, dt, dev(lam), out=q1)
