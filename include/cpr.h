@@ -150,9 +150,10 @@ cpr_status cpr_limit(cpr_ctx* ctx, double* q, int32_t* flags, int32_t* n_trouble
  * map, including the derivative of Rusanov's wave-speed bound
  * lam = max(|u_n|+c) over the two face states (derivative of |u_n| at 0 is
  * +1; where the two speeds tie to 1e-12 relative, the mean of the two
- * sides' gradients is used). In CPR_FP32_BULK contexts the transpose is
- * evaluated in float32 (as the residual is) and its two sweep parts are
- * summed in float64. q, v, out: device float64 states; out must not alias
+ * sides' gradients is used). In CPR_FP32_BULK contexts J^T v is evaluated
+ * in float32 (as the residual is, from q and v rounded to float32) and
+ * combined with v, x and y in float64. q, v, out: device float64 states;
+ * out must not alias
  * q or v. For CPR_SCHEME_GLL_CHAIN the divergence A(q_i) (Dq)_i transposes
  * into sum_i D_il A(q_i)^T a_i plus the flux's second derivatives
  * d/dq [a_l . A(q) (Dq)_l] at q_l (a = -(2/h) v), evaluated together on

@@ -1,7 +1,10 @@
 // Discrete adjoint of the CPR residual: out = alpha v + delta J(q)^T v +
 // beta x + gam y, J = dR/dq of the residual of cpr_stage.hip. The line
 // algebra runs in the residual's compute type R (float64, or float32 for the
-// FP32-bulk residual); q, v, x, y, out and the combination are float64.
+// FP32-bulk residual); q, v, x, y, out and the combination are float64. In
+// float32 the LDS images of q and v are float32 too, which halves the
+// kernel's LDS (at P=4: 54 instead of 108 KB, three workgroups per CU
+// instead of one), and the epilogue adds alpha v from the float64 state.
 //
 // Same tile and lane layout as the forward stage kernel: an 8x8 element
 // tile per workgroup, wave w on line w of every element. Each line is the
@@ -21,6 +24,8 @@
 // reciprocal (hardware estimate and two Newton steps, about 1 ulp). The
 // paper (arXiv:1709.01619) has no adjoint; this transposes its Section 2.2
 // residual operator.
+#include <type_traits>
+
 #include "cpr_device.h"
 
 namespace cpr {
@@ -223,8 +228,12 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
   constexpr int NSP = N1 * N1;
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;
   constexpr int VS = 64 * S;
-  __shared__ double qs[4 * VS];
-  __shared__ double vs[4 * VS];
+  // LDS images in the compute type: float64 states are rounded to float32
+  // here in FP32-bulk, as the line algebra does anyway
+  using LT = R;
+  constexpr bool F32 = sizeof(R) == 4;
+  __shared__ LT qs[4 * VS];
+  __shared__ LT vs[4 * VS];
   __shared__ R hC[4][kTile][N1][4];  // inside face-state cotangents at tile boundaries
 
   const int tid = threadIdx.x;
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 #pragma unroll
   for (int arr = 0; arr < 2; ++arr) {
     const double* gsrc = arr == 0 ? A.q : A.v;
-    double* lds = arr == 0 ? qs : vs;
+    LT* lds = arr == 0 ? qs : vs;
     if (PAIRS && pairs_ok) {
       double2 t2[TC::NRUN][TC::NIT2];
 #pragma unroll
@@ -273,13 +282,13 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
         const int sg = TC::run(wv, u);
         const int k = sg >> 3, cy = sg & 7;
         const bool ok = sg < 4 * kTile && cy < nay;
-        double* dst = lds + k * VS + cy * kTile * S;
+        LT* dst = lds + k * VS + cy * kTile * S;
 #pragma unroll
         for (int it = 0; it < TC::NIT2; ++it) {
           const int f = 2 * (it * 64 + lane);
           if (ok && f < seg_len) {
-            dst[tc.loff2[it]] = t2[u][it].x;
-            dst[tc.loff2b[it]] = t2[u][it].y;
+            dst[tc.loff2[it]] = (LT)t2[u][it].x;
+            dst[tc.loff2b[it]] = (LT)t2[u][it].y;
           }
         }
       }
@@ -303,11 +312,11 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
       const int sg = TC::run(wv, u);
       const int k = sg >> 3, cy = sg & 7;
       const bool ok = sg < 4 * kTile && cy < nay;
-      double* dst = lds + k * VS + cy * kTile * S;
+      LT* dst = lds + k * VS + cy * kTile * S;
 #pragma unroll
       for (int it = 0; it < TC::NIT; ++it) {
         const int f = it * 64 + lane;
-        if (ok && f < seg_len) dst[tc.loff[it]] = t[u][it];
+        if (ok && f < seg_len) dst[tc.loff[it]] = (LT)t[u][it];
       }
     }
   }
@@ -458,7 +467,10 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
   }
 
   R qrow[4][N1];
-  double vrow[4][N1];  // float64: the combination alpha v below uses it
+  // float64 in FP64 contexts, where the combination alpha v below uses it;
+  // FP32-bulk adds alpha v from the float64 state in the epilogue instead
+  using VT = typename std::conditional<F32, R, double>::type;
+  VT vrow[4][N1];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -470,7 +482,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = (double)oc[k][n];
+    for (int n = 0; n < N1; ++n) qs[k * VS + eY * S + n * N1 + wv] = (LT)oc[k][n];
 
   // ---- row sweep (x) ----
   R orow[4][N1];
@@ -518,113 +530,238 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
       const int a = k * VS + eX * S + wv * N1 + n;
-      const double jt = (double)orow[k][n] + qs[a];
-      qs[a] = A.alpha * vrow[k][n] + A.delta * jt;
+      if constexpr (F32) {
+        qs[a] = orow[k][n] + qs[a];  // J^T v; alpha v and delta follow in float64
+      } else {
+        const double jt = (double)orow[k][n] + qs[a];
+        qs[a] = A.alpha * vrow[k][n] + A.delta * jt;
+      }
     }
   __syncthreads();
 
-  // epilogue: the x and y loads of a wave are issued before its stores
-  // (out may alias x)
-  if (PAIRS && pairs_ok) {
-    double2 xv[TC::NRUN][TC::NIT2], yv[TC::NRUN][TC::NIT2];
+  if constexpr (F32) {
+    // FP32-bulk epilogue: out = alpha v + delta (J^T v) + beta x + gam y in
+    // float64, the float64 inputs one array at a time (all of an array's
+    // loads issued, then accumulated), so that at most two arrays of a
+    // wave's values are live; every load precedes the first store (out may
+    // alias x)
+    if (PAIRS && pairs_ok) {
+      double2 ov[TC::NRUN][TC::NIT2], t[TC::NRUN][TC::NIT2];
 #pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = sg < 4 * kTile && cy < nay;
-      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const LT* img = qs + k * VS + cy * kTile * S;
 #pragma unroll
-      for (int it = 0; it < TC::NIT2; ++it) {
-        const int f = 2 * (it * 64 + lane);
-        const bool in = ok && f < seg_len;
-        xv[u][it] = (in && A.x != nullptr) ? *reinterpret_cast<const double2*>(A.x + gb + f)
-                                           : double2{0.0, 0.0};
-        yv[u][it] = (in && A.y != nullptr) ? *reinterpret_cast<const double2*>(A.y + gb + f)
-                                           : double2{0.0, 0.0};
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = sg < 4 * kTile && cy < nay;
-      const double* img = qs + k * VS + cy * kTile * S;
-#pragma unroll
-      for (int it = 0; it < TC::NIT2; ++it) {
-        const int f = 2 * (it * 64 + lane);
-        if (ok && f < seg_len) {
-          double o0 = img[tc.loff2[it]], o1 = img[tc.loff2b[it]];
-          if (A.x != nullptr) {
-            o0 += A.beta * xv[u][it].x;
-            o1 += A.beta * xv[u][it].y;
-          }
-          if (A.y != nullptr) {
-            o0 += A.gam * yv[u][it].x;
-            o1 += A.gam * yv[u][it].y;
-          }
-          xv[u][it] = double2{o0, o1};
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          ov[u][it] = (ok && f < seg_len) ? double2{(double)img[tc.loff2[it]], (double)img[tc.loff2b[it]]}
+                                          : double2{0.0, 0.0};
         }
       }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = sg < 4 * kTile && cy < nay;
-      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+      for (int arr = 0; arr < 3; ++arr) {
+        const double* src = arr == 0 ? A.v : (arr == 1 ? A.x : A.y);
+        if (src == nullptr) continue;
 #pragma unroll
-      for (int it = 0; it < TC::NIT2; ++it) {
-        const int f = 2 * (it * 64 + lane);
-        if (ok && f < seg_len) *reinterpret_cast<double2*>(A.out + gb + f) = xv[u][it];
+        for (int u = 0; u < TC::NRUN; ++u) {
+          const int sg = TC::run(wv, u);
+          const int k = sg >> 3, cy = sg & 7;
+          const bool ok = sg < 4 * kTile && cy < nay;
+          const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+          for (int it = 0; it < TC::NIT2; ++it) {
+            const int f = 2 * (it * 64 + lane);
+            t[u][it] = (ok && f < seg_len) ? *reinterpret_cast<const double2*>(src + gb + f)
+                                           : double2{0.0, 0.0};
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < TC::NRUN; ++u)
+#pragma unroll
+          for (int it = 0; it < TC::NIT2; ++it) {
+            if (arr == 0) {
+              ov[u][it].x = A.alpha * t[u][it].x + A.delta * ov[u][it].x;
+              ov[u][it].y = A.alpha * t[u][it].y + A.delta * ov[u][it].y;
+            } else {
+              const double c = arr == 1 ? A.beta : A.gam;
+              ov[u][it].x += c * t[u][it].x;
+              ov[u][it].y += c * t[u][it].y;
+            }
+          }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          if (ok && f < seg_len) *reinterpret_cast<double2*>(A.out + gb + f) = ov[u][it];
+        }
+      }
+    } else {
+      double ov[TC::NRUN][TC::NIT], t[TC::NRUN][TC::NIT];
+#pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const LT* img = qs + k * VS + cy * kTile * S;
+#pragma unroll
+        for (int it = 0; it < TC::NIT; ++it) {
+          const int f = it * 64 + lane;
+          ov[u][it] = (ok && f < seg_len) ? (double)img[tc.loff[it]] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int arr = 0; arr < 3; ++arr) {
+        const double* src = arr == 0 ? A.v : (arr == 1 ? A.x : A.y);
+        if (src == nullptr) continue;
+#pragma unroll
+        for (int u = 0; u < TC::NRUN; ++u) {
+          const int sg = TC::run(wv, u);
+          const int k = sg >> 3, cy = sg & 7;
+          const bool ok = sg < 4 * kTile && cy < nay;
+          const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+          for (int it = 0; it < TC::NIT; ++it) {
+            const int f = it * 64 + lane;
+            t[u][it] = (ok && f < seg_len) ? src[gb + f] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < TC::NRUN; ++u)
+#pragma unroll
+          for (int it = 0; it < TC::NIT; ++it) {
+            if (arr == 0)
+              ov[u][it] = A.alpha * t[u][it] + A.delta * ov[u][it];
+            else
+              ov[u][it] += (arr == 1 ? A.beta : A.gam) * t[u][it];
+          }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+#pragma unroll
+        for (int it = 0; it < TC::NIT; ++it) {
+          const int f = it * 64 + lane;
+          if (ok && f < seg_len) A.out[gb + f] = ov[u][it];
+        }
       }
     }
   } else {
-    double xv[TC::NRUN][TC::NIT], yv[TC::NRUN][TC::NIT];
-#pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = sg < 4 * kTile && cy < nay;
-      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
-#pragma unroll
-      for (int it = 0; it < TC::NIT; ++it) {
-        const int f = it * 64 + lane;
-        const bool in = ok && f < seg_len;
-        xv[u][it] = (in && A.x != nullptr) ? A.x[gb + f] : 0.0;
-        yv[u][it] = (in && A.y != nullptr) ? A.y[gb + f] : 0.0;
-      }
-    }
-    // every output value is formed before the first store (see the stage
-    // kernel's epilogue), then one explicit wait, then the stores
-#pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = sg < 4 * kTile && cy < nay;
-      const double* img = qs + k * VS + cy * kTile * S;
-#pragma unroll
-      for (int it = 0; it < TC::NIT; ++it) {
-        const int f = it * 64 + lane;
-        if (ok && f < seg_len) {
-          double o = img[tc.loff[it]];
-          if (A.x != nullptr) o += A.beta * xv[u][it];
-          if (A.y != nullptr) o += A.gam * yv[u][it];
-          xv[u][it] = o;
+    // epilogue: the x and y loads of a wave are issued before its stores
+    // (out may alias x)
+    if (PAIRS && pairs_ok) {
+      double2 xv[TC::NRUN][TC::NIT2], yv[TC::NRUN][TC::NIT2];
+  #pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+  #pragma unroll
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          const bool in = ok && f < seg_len;
+          xv[u][it] = (in && A.x != nullptr) ? *reinterpret_cast<const double2*>(A.x + gb + f)
+                                             : double2{0.0, 0.0};
+          yv[u][it] = (in && A.y != nullptr) ? *reinterpret_cast<const double2*>(A.y + gb + f)
+                                             : double2{0.0, 0.0};
         }
       }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-#pragma unroll
-    for (int u = 0; u < TC::NRUN; ++u) {
-      const int sg = TC::run(wv, u);
-      const int k = sg >> 3, cy = sg & 7;
-      const bool ok = sg < 4 * kTile && cy < nay;
-      const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
-#pragma unroll
-      for (int it = 0; it < TC::NIT; ++it) {
-        const int f = it * 64 + lane;
-        if (ok && f < seg_len) A.out[gb + f] = xv[u][it];
+  #pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const double* img = qs + k * VS + cy * kTile * S;
+  #pragma unroll
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          if (ok && f < seg_len) {
+            double o0 = img[tc.loff2[it]], o1 = img[tc.loff2b[it]];
+            if (A.x != nullptr) {
+              o0 += A.beta * xv[u][it].x;
+              o1 += A.beta * xv[u][it].y;
+            }
+            if (A.y != nullptr) {
+              o0 += A.gam * yv[u][it].x;
+              o1 += A.gam * yv[u][it].y;
+            }
+            xv[u][it] = double2{o0, o1};
+          }
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+  #pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+  #pragma unroll
+        for (int it = 0; it < TC::NIT2; ++it) {
+          const int f = 2 * (it * 64 + lane);
+          if (ok && f < seg_len) *reinterpret_cast<double2*>(A.out + gb + f) = xv[u][it];
+        }
+      }
+    } else {
+      double xv[TC::NRUN][TC::NIT], yv[TC::NRUN][TC::NIT];
+  #pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+  #pragma unroll
+        for (int it = 0; it < TC::NIT; ++it) {
+          const int f = it * 64 + lane;
+          const bool in = ok && f < seg_len;
+          xv[u][it] = (in && A.x != nullptr) ? A.x[gb + f] : 0.0;
+          yv[u][it] = (in && A.y != nullptr) ? A.y[gb + f] : 0.0;
+        }
+      }
+      // every output value is formed before the first store (see the stage
+      // kernel's epilogue), then one explicit wait, then the stores
+  #pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const double* img = qs + k * VS + cy * kTile * S;
+  #pragma unroll
+        for (int it = 0; it < TC::NIT; ++it) {
+          const int f = it * 64 + lane;
+          if (ok && f < seg_len) {
+            double o = img[tc.loff[it]];
+            if (A.x != nullptr) o += A.beta * xv[u][it];
+            if (A.y != nullptr) o += A.gam * yv[u][it];
+            xv[u][it] = o;
+          }
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+  #pragma unroll
+      for (int u = 0; u < TC::NRUN; ++u) {
+        const int sg = TC::run(wv, u);
+        const int k = sg >> 3, cy = sg & 7;
+        const bool ok = sg < 4 * kTile && cy < nay;
+        const size_t gb = k * plane + ((size_t)(J0 + cy) * G.nx + I0) * NSP;
+  #pragma unroll
+        for (int it = 0; it < TC::NIT; ++it) {
+          const int f = it * 64 + lane;
+          if (ok && f < seg_len) A.out[gb + f] = xv[u][it];
+        }
       }
     }
   }
