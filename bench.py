@@ -473,6 +473,21 @@ def profile_legs(a):
             q = vortex_state(s)
             ms = time_steps(s, q, 1e-4, a.steps, a.warmup)
             print(f"scale P=4 1024^2 {prec}: {ms:.4f} ms/step", flush=True)
+    if "riemann" in legs:
+        # a.steps limited steps of the P=2 512^2 four-quadrant Riemann problem
+        # with device dt (the C3 step: 3 stages, 3 limiter passes, the CFL
+        # reduction)
+        import inputs
+        s = Solver(2, 512, 512, 0.0, 1.0, 0.0, 1.0, bc="transmissive", limiter=True,
+                   tvb_m=10.0, cfl=0.1, t_end=0.3)
+        x, y = s.coords()
+        q = torch.from_numpy(inputs.riemann_quadrants(x.cpu().numpy(),
+                                                      y.cpu().numpy())).cuda()
+        s.set_time(0.0)
+        for _ in range(a.steps):
+            s.step(q, 0.0, limit=True)
+        torch.cuda.synchronize()
+        print(f"riemann P=2 512^2 limited: {a.steps} steps, t = {s.get_time()[0]:.4f}", flush=True)
     if "adjoint" in legs:
         # one checkpoint segment of the P=4 1024^2 adjoint workload (a.steps
         # steps, checkpoint a.steps) and of the P=3 128^2 one, forward and
@@ -504,8 +519,8 @@ def main(argv=None):
                     help="skip the t=10 error runs, the adjoint and the P=4 legs")
     ap.add_argument("--legs", default="all",
                     help="comma list of legs to run for profiling: main, scale, chain, "
-                         "adjoint, copy (a 1 GiB device copy that calibrates HBM byte "
-                         "counters); "
+                         "adjoint, riemann, copy (a 1 GiB device copy that calibrates HBM "
+                         "byte counters); "
                          "prints a short text report instead of the JSON line")
     a = ap.parse_args(argv)
     if a.legs != "all":
