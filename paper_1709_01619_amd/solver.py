@@ -139,6 +139,24 @@ class Solver:
                                           1 if limit else 0), "cpr_rk3_step")
         return q
 
+    def capture_steps(self, q, dt, nsteps, limit=False):
+        """Record nsteps SSP-RK3 steps of q (in place, as step()) into a HIP
+        graph and return it (a torch.cuda.CUDAGraph); each replay() then
+        advances q by nsteps steps with one graph launch, which removes the
+        per-kernel launch cost where the mesh is small. The step path only
+        launches kernels (no allocation, copy, memset or synchronisation), so
+        it records as it runs; q must stay the same tensor, and a device dt
+        (dt <= 0) reads the context's time as each replay reaches it."""
+        torch = _torch()
+        if nsteps < 1:
+            raise ValueError("nsteps must be >= 1")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.device(self.device):
+            with torch.cuda.graph(g):
+                for _ in range(nsteps):
+                    self.step(q, dt, limit=limit)
+        return g
+
     def limit(self, q, flags=None, count=False):
         torch = _torch()
         self._enter()

@@ -1,0 +1,71 @@
+"""HIP-graph capture of the step path (Solver.capture_steps): each replay
+of a recorded run equals the same run launched kernel by kernel, bit for
+bit (the same kernels on the same data), with eager work and
+synchronisations between the replays; recording itself runs nothing."""
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import cpr
+from tests.gpu_util import dev, host, make_solver, say, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("P,prec", [(1, "fp64"), (2, "fp64"), (3, "fp64"), (3, "fp32_bulk"),
+                                    (4, "fp64")])
+def test_captured_steps_equal_eager(P, prec):
+    t = torch()
+    g = cpr.Grid(P=P, nx=20, ny=20)
+    x, y = g.coords()
+    q0 = inputs.Vortex().conserved(x, y)
+    say("graph steps", P, prec)
+    s = make_solver(g, precision=prec)
+    qg = dev(q0)
+    graph = s.capture_steps(qg, 1e-3, 10)
+    t.cuda.synchronize()
+    assert np.array_equal(host(qg), q0)
+    start = dev(q0)
+    for _ in range(3):
+        qe = start.clone()
+        for _ in range(10):
+            s.step(qe, 1e-3)
+        t.cuda.synchronize()
+        qg.copy_(start)
+        graph.replay()
+        t.cuda.synchronize()
+        assert t.equal(qg, qe)
+        start = qe + 0.0   # the next replay starts from a new state
+
+
+def test_captured_limited_device_dt_steps_equal_eager():
+    """The C3 step (limiter after every stage, CFL dt formed on the device)
+    on the four-quadrant Riemann problem: replays from the same state and
+    time reach the same state, time and troubled count as eager steps."""
+    t = torch()
+    g = cpr.Grid(P=2, nx=32, ny=32, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc="transmissive")
+    x, y = g.coords()
+    q0 = inputs.riemann_quadrants(x, y)
+    say("graph limited device-dt steps")
+    s = make_solver(g, limiter=True, tvb_m=10.0, cfl=0.1, t_end=0.3)
+    qs = dev(q0)
+    s.limit(qs)
+    qg = qs.clone()
+    graph = s.capture_steps(qg, 0.0, 8, limit=True)
+    for _ in range(3):
+        s.set_time(0.0)
+        s.troubled_total(reset=True)
+        qe = qs.clone()
+        for _ in range(8):
+            s.step(qe, 0.0, limit=True)
+        te, dte = s.get_time()
+        ne = s.troubled_total(reset=True)
+        s.set_time(0.0)
+        qg.copy_(qs)
+        graph.replay()
+        tg, dtg = s.get_time()
+        ng = s.troubled_total(reset=True)
+        assert t.equal(qg, qe)
+        assert (tg, dtg, ng) == (te, dte, ne)
+        assert te > 0.0 and ne > 0
