@@ -12,6 +12,8 @@ initial data. The metric is DOF-updates per second per RK stage (one
 unknown advanced by one stage), FP64 (the reported value) and FP32-bulk,
 with the L2 density error each reaches at t=10 (one period) on 64^2, 128^2
 and 256^2, and the hand-written adjoint's seconds per step on P=3 128^2.
+The timed steps run as one HIP graph replay (Solver.capture_steps); the
+same steps launched kernel by kernel are reported under "eager".
 
 Printed: one JSON line (rank 0). Extra objects:
   roofline      the stage kernel against HBM bandwidth (algorithmic bytes:
