@@ -235,6 +235,32 @@ def test_residual_vjp_fp32_bulk(P, bc):
     assert err <= 64 * 2.0 ** -24 * scale
 
 
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_adjoint_step_fp32_bulk(P):
+    """FP32-bulk adjoint step (float32 transposes, float64 combinations with
+    v, x and y) against the oracle's float64 step. Each transpose J(q_s)^T
+    lam_s enters scaled by at most dt, and an error in lam2 or lam1 reaches
+    lam_n with a weight of at most 1 + dt |J|; the bound is twice the sum
+    over the three transposes of dt 64 2^-24 times their term scale, with
+    lam2 and lam1 taken from the oracle."""
+    g = cpr.Grid(P=P, nx=10, ny=9)
+    x, y = g.coords()
+    q = inputs.Vortex().conserved(x, y)
+    lam = np.random.default_rng(6600 + P).standard_normal(g.shape)
+    dt = 0.01
+    say("adjoint step fp32_bulk", P)
+    ref = adjoint.rk3_adjoint_step(q, dt, lam, g)
+    out = host(make_solver(g, precision="fp32_bulk").adjoint_step(dev(q), dt, dev(lam)))
+    err = np.max(np.abs(out - ref))
+    qn, q1, q2, _ = cpr.rk3_stages(q, dt, g)
+    lam2 = (2.0 / 3.0) * (lam + dt * adjoint.residual_vjp(q2, lam, g))
+    lam1 = 0.25 * (lam2 + dt * adjoint.residual_vjp(q1, lam2, g))
+    scale = sum(_vjp_fp32_scale(qs, ls, g) for qs, ls in ((q2, lam), (q1, lam2), (qn, lam1)))
+    bound = 2 * dt * 64 * 2.0 ** -24 * scale
+    print(f"fp32_bulk adjoint step P={P}: max err {err:.3e}, bound {bound:.3e}")
+    assert err <= bound
+
+
 def test_rollout_gradient_fp32_bulk():
     """FP32-bulk rollout gradient (float32 residual and transposes, float64
     state and lam) against the oracle's float64 gradient on the perturbed
