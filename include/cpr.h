@@ -149,7 +149,8 @@ cpr_status cpr_limit(cpr_ctx* ctx, double* q, int32_t* flags, int32_t* n_trouble
 /* out = (dR/dq)^T v at state q: the exact transpose of cpr_residual's
  * map, including the derivative of Rusanov's wave-speed bound
  * lam = max(|u_n|+c) over the two face states (derivative of |u_n| at 0 is
- * +1; where the two speeds tie to 1e-12 relative, the mean of the two
+ * +1; where the two speeds tie to 1e-12 relative (2^-17 in CPR_FP32_BULK
+ * contexts, above the float32 rounding of the speeds), the mean of the two
  * sides' gradients is used). In CPR_FP32_BULK contexts J^T v is evaluated
  * in float32 (as the residual is, from q and v rounded to float32) and
  * combined with v, x and y in float64. q, v, out: device float64 states;

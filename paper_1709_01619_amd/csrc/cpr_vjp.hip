@@ -16,7 +16,9 @@
 // where the cotangent of a face flux is the sum of the sigmas of the two
 // elements sharing the face, pushed through the transposed Rusanov flux
 // (including the derivative of lam = max(|u_n| + c), d|u_n|/du_n = +1 at 0;
-// where the two one-sided speeds tie to 1e-12 relative, the gradient of max
+// where the two one-sided speeds tie (to 1e-12 relative in float64, 2^-17
+// in float32: a tie must be recognised whichever side the rounding of the
+// speeds favours, so the threshold sits above that rounding), the gradient of max
 // is the mean of both sides' gradients). The two sides' contributions of an interior
 // face are exchanged between adjacent lanes by wave shuffles; tile-boundary
 // faces are finished by boundary lanes that read the neighbour element's line
@@ -75,6 +77,10 @@ __device__ __forceinline__ void flux_jac_t(const T q[4], R gam, const T s[4], T 
   out[3] = gm1 * s[n] + gam * un * s[3];
 }
 
+// Relative gap below which the two Rusanov speeds count as tied.
+__device__ __forceinline__ constexpr double tie_rel(double) { return 1e-12; }
+__device__ __forceinline__ constexpr float tie_rel(float) { return 0x1p-17f; }
+
 // Gradient of |u_n| + c with respect to q.
 template <int AX, typename R>
 __device__ __forceinline__ void wave_speed_grad(const R q[4], R gam, R c, R g[4]) {
@@ -102,7 +108,7 @@ __device__ __forceinline__ void rusanov_vjp(const R qL[4], const R qR[4], const 
   const R cLs = sqrt_pos(gam * pL * irL), cRs = sqrt_pos(gam * pR * irR);
   const R lL = fabs(qL[n] * irL) + cLs, lR = fabs(qR[n] * irR) + cRs;
   const R lam = lL >= lR ? lL : lR;
-  const bool tie = fabs(lL - lR) <= R(1e-12) * lam;
+  const bool tie = fabs(lL - lR) <= tie_rel(R(0)) * lam;
   const R wl = tie ? R(0.5) : (lL > lR ? R(1) : R(0));
   const R wr = R(1) - wl;
   R jump = R(0);
