@@ -746,7 +746,10 @@ def main(argv=None):
                       "instead of replayed from one HIP graph"),
         "fp32_bulk": {"value": res["fp32_bulk"]["dof_updates_per_s"],
                       "ms_per_step": res["fp32_bulk"]["ms_per_step"],
-                      "speedup_vs_fp64": res["fp32_bulk"]["dof_updates_per_s"] / f64["dof_updates_per_s"]},
+                      "speedup_vs_fp64": res["fp32_bulk"]["dof_updates_per_s"] / f64["dof_updates_per_s"],
+                      "hbm_frac": round(bytes_per_launch / (res["fp32_bulk"]["stage_launch_us"]
+                                                            * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                      "eager": res["fp32_bulk"]["eager"]},
         "l2_error_t10": l2,
         "adjoint": adj,
         "scale_p4_1024": scale,
