@@ -135,6 +135,39 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+def cpu_other_configs():
+    """The oracle on two smaller workloads, for context beside their GPU
+    figures: the P=2 20x20 vortex run (100 steps, in full) and one adjoint
+    step of the P=3 128x128 vortex (forward stage recompute and the three
+    transposes). NumPy float64, one BLAS thread."""
+    import inputs
+    from oracle import adjoint, cpr
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:
+        limiter = None
+    out = {}
+    g = cpr.Grid(P=2, nx=20, ny=20)
+    x, y = g.coords()
+    q = inputs.Vortex().conserved(x, y)
+    t0 = time.perf_counter()
+    cpr.run(q, g, 1e-3, 100)
+    el = time.perf_counter() - t0
+    out["c1_small"] = {"s_per_step": el / 100, "sample": "all 100 steps"}
+    g = cpr.Grid(P=3, nx=128, ny=128)
+    x, y = g.coords()
+    q = inputs.Vortex().conserved(x, y)
+    lam = q * 1e-3
+    t0 = time.perf_counter()
+    adjoint.rk3_adjoint_step(q, 1e-3, lam, g)
+    el = time.perf_counter() - t0
+    out["adjoint_p3_128"] = {"s_per_adjoint_step": el, "sample": "one adjoint step"}
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    return out
+
+
 def cpu_baseline(P=3, n=256, steps=None, budget_s=15.0):
     """The oracle (NumPy FP64, one BLAS thread) on the same workload: a
     bounded number of RK3 steps on the full 256^2 mesh."""
@@ -719,6 +752,8 @@ def main(argv=None):
     if not a.no_cpu:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline()
+        if not a.quick:
+            cpu["other_configs"] = cpu_other_configs()
         log("cpu", cpu)
 
     line = {
