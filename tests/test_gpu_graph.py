@@ -69,3 +69,25 @@ def test_captured_limited_device_dt_steps_equal_eager():
         assert t.equal(qg, qe)
         assert (tg, dtg, ng) == (te, dte, ne)
         assert te > 0.0 and ne > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
+def test_headline_size_graph_replay_equals_eager(prec):
+    """At the timed workload's full size (P=3 vortex on 256x256, the
+    benchmark's dt) the benchmark's graph replay gives the same state, bit
+    for bit, as the same steps launched kernel by kernel; the full-size
+    parity tests check the kernel-by-kernel state against the oracle."""
+    t = torch()
+    g = cpr.Grid(P=3, nx=256, ny=256)
+    x, y = g.coords()
+    q0 = dev(inputs.Vortex().conserved(x, y))
+    say("headline graph replay", prec)
+    s = make_solver(g, precision=prec)
+    qe = q0.clone()
+    for _ in range(12):
+        s.step(qe, 5.8e-4)
+    qg = q0.clone()
+    graph = s.capture_steps(qg, 5.8e-4, 12)
+    graph.replay()
+    t.cuda.synchronize()
+    assert t.equal(qg, qe)
