@@ -91,3 +91,27 @@ def test_headline_size_graph_replay_equals_eager(prec):
     graph.replay()
     t.cuda.synchronize()
     assert t.equal(qg, qe)
+
+
+def test_capture_rejects_what_a_step_rejects():
+    """Recording runs the step's own argument checks: a limited step on a
+    context without a limiter, or a device dt without a CFL number, raises
+    the library's error while recording; the state is left untouched."""
+    from paper_1709_01619_amd import _lib
+    g = cpr.Grid(P=2, nx=8, ny=8)
+    x, y = g.coords()
+    q0 = inputs.Vortex().conserved(x, y)
+    say("graph capture errors")
+    s = make_solver(g)
+    q = dev(q0)
+    with pytest.raises(_lib.CprError) as ei:
+        s.capture_steps(q, 1e-3, 2, limit=True)
+    assert ei.value.status == _lib.CPR_EUNSUPPORTED
+    with pytest.raises(_lib.CprError) as ei:
+        s.capture_steps(q, 0.0, 2)
+    assert ei.value.status == _lib.CPR_EINVAL
+    with pytest.raises(ValueError):
+        s.capture_steps(q, 1e-3, 0)
+    assert np.array_equal(host(q), q0)
+    s.step(q, 1e-3)   # the context still works after the aborted recordings
+    torch().cuda.synchronize()
