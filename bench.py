@@ -389,6 +389,28 @@ def paper_scheme():
                     "hbm_frac": round(ach / HBM_PEAK_GBS, 4)}
         log(scheme, P, n, prec, out[key])
         del s, q
+    # the residual's transpose (one launch of cpr_residual_vjp) per scheme, P=3 256^2 FP64
+    import torch
+    vjp = {}
+    for scheme in ("gl_lp", "gll_chain", "gll_lp"):
+        s = Solver(3, 256, 256, scheme=scheme)
+        q = vortex_state(s)
+        v = torch.ones_like(q)
+        o = torch.empty_like(q)
+        for _ in range(3):
+            s.residual_vjp(q, v, o)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(50):
+            s.residual_vjp(q, v, o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        vjp[scheme] = {"us_per_launch": e0.elapsed_time(e1) / 50 * 1e3}
+        del s, q, v, o
+    out["residual_vjp_p3_256_fp64"] = vjp
+    log("vjp per scheme", vjp)
     V = inputs.Vortex(eps=5.0, lo=-5.0, hi=5.0, u_inf=1.0, v_inf=0.0, center=(0.0, 0.0))
     rows = []
     for scheme, col in (("gll_chain", 3), ("gl_lp", 4), ("gll_lp", 5)):
