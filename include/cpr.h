@@ -241,11 +241,40 @@ cpr_status cpr_get_time(cpr_ctx* ctx, double* t_host, double* last_dt_host);
  * *total_host; reset != 0 clears the total after reading. */
 cpr_status cpr_troubled_total(cpr_ctx* ctx, int64_t* total_host, int32_t reset);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * unlimited SSP-RK3 step of fixed size dt, as cpr_rk3_step(ctx, q, dt, 0)
+ * on a context made from *cfg gives bit for bit, but without a context.
+ * It allocates nothing: the two stage states live in a static device array
+ * of the library, 2 x 32 MiB plus a few words, which every GPU the
+ * library runs on holds until the process ends. The array's address is
+ * looked up on the first call on each device (make that first call
+ * outside graph capture).
+ *   cfg     configuration as for cpr_init (host pointer, read during the
+ *           call only); limiter must be CPR_LIM_NONE (CPR_EUNSUPPORTED
+ *           otherwise).
+ *   stream  hipStream_t the kernels are enqueued on, or NULL.
+ *   q       device float64 state (layout above), advanced in place.
+ *   dt      step size, finite and > 0 (no device-computed dt).
+ *   err_flag nullable device int32 the kernels set to 1 on a non-physical
+ *           state; the caller clears and reads it. NULL: the flag goes to
+ *           a word of the static array, cleared by the call, and is lost.
+ * Returns CPR_EINVAL for an invalid cfg, NULL q or bad dt, and
+ * CPR_EUNSUPPORTED when the state exceeds 2^22 float64 values (32 MiB,
+ * e.g. P = 3 on 256 x 256 elements); nothing is enqueued then, and
+ * cpr_last_error(NULL) gives the reason. Asynchronous otherwise. Every
+ * call on one GPU uses the same static array, so calls that overlap on one
+ * GPU (several streams or host threads at once) race; serialise them. */
+cpr_status cpr_rk3_step_static(const cpr_config* cfg, void* stream, double* q, double dt,
+                               int32_t* err_flag);
+
 /* Wait for the context's stream; return any deferred device error. */
 cpr_status cpr_sync(cpr_ctx* ctx);
 
 const char* cpr_status_string(cpr_status s);
-/* Text of the context's last error (never NULL; "" when none). */
+/* Text of the context's last error (never NULL; "" when none). With ctx
+ * NULL: the last error of a context-free call (cpr_rk3_step_static) on the
+ * calling host thread. */
 const char* cpr_last_error(const cpr_ctx* ctx);
 
 #ifdef __cplusplus

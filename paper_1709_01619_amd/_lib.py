@@ -27,7 +27,7 @@ SYMBOLS = (
     "cpr_residual_vjp", "cpr_adjoint_step", "cpr_rk3_step_stages", "cpr_adjoint_step_stages",
     "cpr_max_wavespeed", "cpr_integrals", "cpr_l2_diff",
     "cpr_point_coords", "cpr_tables", "cpr_scheme_tables", "cpr_set_time", "cpr_get_time", "cpr_troubled_total", "cpr_sync",
-    "cpr_status_string", "cpr_last_error",
+    "cpr_status_string", "cpr_last_error", "cpr_rk3_step_static",
 )
 
 
@@ -103,6 +103,8 @@ def load(path: str = LIB_PATH):
         "cpr_sync": (c_int32, [c_void_p]),
         "cpr_status_string": (ctypes.c_char_p, [c_int32]),
         "cpr_last_error": (ctypes.c_char_p, [c_void_p]),
+        "cpr_rk3_step_static": (c_int32, [P(CprConfig), c_void_p, c_void_p, c_double,
+                                          c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -38,6 +38,69 @@ struct cpr_ctx {
   char last_error[512];
 };
 
+namespace cpr {
+
+thread_local char t_last_error[256];
+
+void set_thread_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(t_last_error, sizeof(t_last_error), fmt, ap);
+  va_end(ap);
+}
+
+bool config_valid(const cpr_config& c) {
+  if (c.abi_version != CPR_ABI_VERSION) return false;
+  if (c.order_p < 1 || c.order_p > kMaxP) return false;
+  if (c.nx < 1 || c.ny < 1 || c.nx > (1 << 20) || c.ny > (1 << 20)) return false;
+  // element means are indexed k*nx*ny + e in 32-bit arithmetic
+  if ((int64_t)c.nx * c.ny > ((int64_t)1 << 29)) return false;
+  if (!(std::isfinite(c.x0) && std::isfinite(c.x1) && c.x1 > c.x0)) return false;
+  if (!(std::isfinite(c.y0) && std::isfinite(c.y1) && c.y1 > c.y0)) return false;
+  if (c.bc != CPR_BC_PERIODIC && c.bc != CPR_BC_TRANSMISSIVE) return false;
+  if (c.precision != CPR_FP64 && c.precision != CPR_FP32_BULK) return false;
+  if (!(std::isfinite(c.gamma) && c.gamma > 1.0)) return false;
+  if (c.limiter != CPR_LIM_NONE && c.limiter != CPR_LIM_TVB_CHAR) return false;
+  if (c.scheme != CPR_SCHEME_GL_LP && c.scheme != CPR_SCHEME_GLL_CHAIN &&
+      c.scheme != CPR_SCHEME_GLL_LP)
+    return false;
+  if (!(std::isfinite(c.tvb_m) && c.tvb_m >= 0.0)) return false;
+  if (!(std::isfinite(c.cfl) && c.cfl >= 0.0)) return false;
+  if (!std::isfinite(c.t_end)) return false;
+  return true;
+}
+
+Geometry config_geometry(const cpr_config& c) {
+  Geometry g{};
+  g.nx = c.nx;
+  g.ny = c.ny;
+  g.ntx = (c.nx + kTile - 1) / kTile;
+  g.nty = (c.ny + kTile - 1) / kTile;
+  g.dx = (c.x1 - c.x0) / c.nx;
+  g.dy = (c.y1 - c.y0) / c.ny;
+  g.gamma = c.gamma;
+  g.periodic = c.bc == CPR_BC_PERIODIC ? 1 : 0;
+  return g;
+}
+
+void rk3_stage_args(const Tables1D& T, int P, int stage, const double* q, const double* src,
+                    double* dst, double dt, int* err, StageArgs* s) {
+  static const double ka[3] = {0.0, 0.75, 1.0 / 3.0}, kb[3] = {1.0, 0.25, 2.0 / 3.0};
+  *s = StageArgs{};
+  for (int i = 0; i <= P; ++i) s->w[i] = T.w[i];
+  s->q_src = src;
+  s->q_n = stage == 0 ? nullptr : q;
+  s->q_dst = dst;
+  s->a = ka[stage];
+  s->b = kb[stage];
+  s->dt = dt;
+  s->err = err;
+  const uintptr_t any = (uintptr_t)src | (uintptr_t)q | (uintptr_t)dst;
+  s->vec = (any & 15) == 0;
+}
+
+}  // namespace cpr
+
 namespace {
 
 void set_err(cpr_ctx* c, const char* fmt, ...) {
@@ -158,7 +221,7 @@ const char* cpr_status_string(cpr_status s) {
   }
 }
 
-const char* cpr_last_error(const cpr_ctx* ctx) { return ctx ? ctx->last_error : ""; }
+const char* cpr_last_error(const cpr_ctx* ctx) { return ctx ? ctx->last_error : t_last_error; }
 
 cpr_status cpr_tables(int32_t order_p, double* xi, double* w, double* gLp, double* gRp) {
   return cpr_scheme_tables(CPR_SCHEME_GL_LP, order_p, xi, w, gLp, gRp);
@@ -183,23 +246,7 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   if (out == nullptr || cfg == nullptr) return CPR_EINVAL;
   *out = nullptr;
   const cpr_config& c = *cfg;
-  if (c.abi_version != CPR_ABI_VERSION) return CPR_EINVAL;
-  if (c.order_p < 1 || c.order_p > kMaxP) return CPR_EINVAL;
-  if (c.nx < 1 || c.ny < 1 || c.nx > (1 << 20) || c.ny > (1 << 20)) return CPR_EINVAL;
-  // element means are indexed k*nx*ny + e in 32-bit arithmetic
-  if ((int64_t)c.nx * c.ny > ((int64_t)1 << 29)) return CPR_EINVAL;
-  if (!(std::isfinite(c.x0) && std::isfinite(c.x1) && c.x1 > c.x0)) return CPR_EINVAL;
-  if (!(std::isfinite(c.y0) && std::isfinite(c.y1) && c.y1 > c.y0)) return CPR_EINVAL;
-  if (c.bc != CPR_BC_PERIODIC && c.bc != CPR_BC_TRANSMISSIVE) return CPR_EINVAL;
-  if (c.precision != CPR_FP64 && c.precision != CPR_FP32_BULK) return CPR_EINVAL;
-  if (!(std::isfinite(c.gamma) && c.gamma > 1.0)) return CPR_EINVAL;
-  if (c.limiter != CPR_LIM_NONE && c.limiter != CPR_LIM_TVB_CHAR) return CPR_EINVAL;
-  if (c.scheme != CPR_SCHEME_GL_LP && c.scheme != CPR_SCHEME_GLL_CHAIN &&
-      c.scheme != CPR_SCHEME_GLL_LP)
-    return CPR_EINVAL;
-  if (!(std::isfinite(c.tvb_m) && c.tvb_m >= 0.0)) return CPR_EINVAL;
-  if (!(std::isfinite(c.cfl) && c.cfl >= 0.0)) return CPR_EINVAL;
-  if (!std::isfinite(c.t_end)) return CPR_EINVAL;
+  if (!config_valid(c)) return CPR_EINVAL;
 
   cpr_ctx* x = new (std::nothrow) cpr_ctx();
   if (x == nullptr) return CPR_ENOMEM;
@@ -211,14 +258,7 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
     return CPR_EINVAL;
   }
   const int n1 = c.order_p + 1;
-  x->geo.nx = c.nx;
-  x->geo.ny = c.ny;
-  x->geo.ntx = (c.nx + kTile - 1) / kTile;
-  x->geo.nty = (c.ny + kTile - 1) / kTile;
-  x->geo.dx = (c.x1 - c.x0) / c.nx;
-  x->geo.dy = (c.y1 - c.y0) / c.ny;
-  x->geo.gamma = c.gamma;
-  x->geo.periodic = c.bc == CPR_BC_PERIODIC ? 1 : 0;
+  x->geo = config_geometry(c);
   x->n_elem = (size_t)c.nx * (size_t)c.ny;
   x->n_state = 4 * x->n_elem * (size_t)(n1 * n1);
   if ((size_t)x->geo.ntx * (size_t)x->geo.nty >= (size_t)1 << 31) {

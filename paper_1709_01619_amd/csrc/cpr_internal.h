@@ -6,6 +6,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "cpr.h"
+
 namespace cpr {
 
 constexpr int kMaxP = 4;
@@ -113,5 +115,15 @@ hipError_t launch_weighted_sum(int P, const Geometry& g, const Tables1D& T, int 
 hipError_t launch_coords(int P, const Geometry& g, const Tables1D& T, double x0, double y0,
                          double* x, double* y, hipStream_t s);
 hipError_t launch_fill_int(int* p, int v, size_t n, hipStream_t s);
+
+// Host helpers of the C ABI (cpr_api.hip).
+bool config_valid(const cpr_config& c);
+Geometry config_geometry(const cpr_config& c);
+// Arguments of stage `stage` (0, 1, 2) of one unlimited SSP-RK3 step of
+// fixed size dt from q: reads src (and q for stages 1, 2), writes dst.
+void rk3_stage_args(const Tables1D& T, int P, int stage, const double* q, const double* src,
+                    double* dst, double dt, int* err, StageArgs* s);
+// Error text of context-free calls, per host thread (cpr_last_error(NULL)).
+void set_thread_error(const char* fmt, ...);
 
 }  // namespace cpr
