@@ -19,10 +19,12 @@ Modules
            CFL time step (Section 4), integrals and error norms.
   limiter  TVB minmod limiter on characteristic variables (Section 2.6).
   adjoint  Hand-written discrete adjoint of the residual and of one RK step.
+  deviation The same residual written as deviations from a per-line
+           reference state (the form the float32 residual evaluates).
 
 Parity status: every function is pinned by tests/test_oracle_*.py against
 closed forms, invariants, library routines or a 50-digit brute force,
 except where its docstring says "parity unpinned".
 """
 
-from . import tables, euler, cpr, limiter, adjoint  # noqa: F401
+from . import tables, euler, cpr, limiter, adjoint, deviation  # noqa: F401
