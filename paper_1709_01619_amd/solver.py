@@ -9,6 +9,7 @@ GPU raises.
 from __future__ import annotations
 
 import ctypes
+import weakref
 from ctypes import byref, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
@@ -24,6 +25,24 @@ SCHEME = {"gl_lp": _lib.CPR_SCHEME_GL_LP, "gll_chain": _lib.CPR_SCHEME_GLL_CHAIN
 def _torch():
     import torch
     return torch
+
+
+class StepGraph:
+    """A run of SSP-RK3 steps recorded into a HIP graph (Solver.capture_steps).
+    The recorded kernels read and write the state q and the solver's scratch
+    through raw device pointers, so the StepGraph holds references to both:
+    neither can be freed while it exists."""
+
+    def __init__(self, graph, solver, q):
+        self.graph = graph
+        self.solver = solver
+        self.q = q
+
+    def replay(self):
+        """Advance q by the recorded steps (one graph launch)."""
+        if not self.solver._ctx.value:
+            raise RuntimeError("the solver of this graph was closed")
+        self.graph.replay()
 
 
 class Solver:
@@ -59,6 +78,7 @@ class Solver:
                                _lib.CPR_LIM_TVB_CHAR if limiter else _lib.CPR_LIM_NONE,
                                float(tvb_m), float(cfl), float(t_end), SCHEME[scheme])
         self._ctx = c_void_p()
+        self._graphs = weakref.WeakSet()
         with torch.cuda.device(self.device):
             st = self.lib.cpr_init(byref(cfg), c_void_p(self._stream()), byref(self._ctx))
         _lib.check(st, None, "cpr_init")
@@ -72,7 +92,12 @@ class Solver:
         self.lib.cpr_set_stream(self._ctx, c_void_p(self._stream()))
 
     def close(self):
+        """Release the context and its scratch. Raises while a StepGraph
+        recorded from this solver is alive (its kernels use the scratch)."""
         if getattr(self, "_ctx", None) and self._ctx.value:
+            if len(getattr(self, "_graphs", ())) > 0:
+                raise RuntimeError("close(): graphs recorded from this solver are alive; "
+                                   "delete them first")
             self.lib.cpr_destroy(self._ctx)
             self._ctx = c_void_p()
 
@@ -141,12 +166,14 @@ class Solver:
 
     def capture_steps(self, q, dt, nsteps, limit=False):
         """Record nsteps SSP-RK3 steps of q (in place, as step()) into a HIP
-        graph and return it (a torch.cuda.CUDAGraph); each replay() then
-        advances q by nsteps steps with one graph launch, which removes the
-        per-kernel launch cost where the mesh is small. The step path only
-        launches kernels (no allocation, copy, memset or synchronisation), so
-        it records as it runs; q must stay the same tensor, and a device dt
-        (dt <= 0) reads the context's time as each replay reaches it."""
+        graph and return it as a StepGraph; each replay() then advances q by
+        nsteps steps with one graph launch, which removes the per-kernel
+        launch cost where the mesh is small. The step path only launches
+        kernels (no allocation, copy, memset or synchronisation), so it
+        records as it runs; a device dt (dt <= 0) reads the context's time as
+        each replay reaches it. The recorded kernels hold raw pointers to q
+        and to this solver's scratch, so the StepGraph keeps both alive, and
+        close() refuses while a StepGraph of this solver exists."""
         torch = _torch()
         if nsteps < 1:
             raise ValueError("nsteps must be >= 1")
@@ -155,7 +182,9 @@ class Solver:
             with torch.cuda.graph(g):
                 for _ in range(nsteps):
                     self.step(q, dt, limit=limit)
-        return g
+        sg = StepGraph(g, self, q)
+        self._graphs.add(sg)
+        return sg
 
     def limit(self, q, flags=None, count=False):
         torch = _torch()

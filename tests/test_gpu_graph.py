@@ -115,3 +115,38 @@ def test_capture_rejects_what_a_step_rejects():
     assert np.array_equal(host(q), q0)
     s.step(q, 1e-3)   # the context still works after the aborted recordings
     torch().cuda.synchronize()
+
+
+def test_graph_keeps_its_solver_and_state_alive():
+    """A recorded graph's kernels use the solver's scratch and the state
+    through raw pointers: the StepGraph holds both, so dropping every other
+    reference frees neither; close() refuses while the graph exists, and the
+    replay equals eager steps on a fresh solver."""
+    import gc
+    import weakref
+
+    t = torch()
+    g = cpr.Grid(P=2, nx=16, ny=12)
+    x, y = g.coords()
+    q0 = inputs.Vortex().conserved(x, y)
+    say("graph lifetime")
+    s = make_solver(g)
+    qg = dev(q0)
+    graph = s.capture_steps(qg, 1e-3, 4)
+    with pytest.raises(RuntimeError):
+        s.close()
+    ws, wq = weakref.ref(s), weakref.ref(qg)
+    del s, qg
+    gc.collect()
+    assert ws() is not None and wq() is not None
+    graph.replay()
+    t.cuda.synchronize()
+    ref = make_solver(g)
+    qe = dev(q0)
+    for _ in range(4):
+        ref.step(qe, 1e-3)
+    t.cuda.synchronize()
+    assert t.equal(graph.q, qe)
+    del graph
+    gc.collect()
+    assert ws() is None
