@@ -7,6 +7,8 @@ orders; the per-value rounding difference is a few ulps of the largest
 intermediate, (2/dx)(||D||_inf + 2||g'||_inf) max|F| ~ 1e2..1e3 times
 2.2e-16, far below the bound."""
 
+import math
+
 import numpy as np
 import pytest
 
@@ -219,3 +221,33 @@ def test_misaligned_states_match_aligned(nx, P, prec):
         s.step(qa, 1e-3)
         s.step(qm, 1e-3)
     assert np.array_equal(host(qa), host(qm))
+
+
+def test_init_out_of_memory_leaks_nothing():
+    """cpr_init on a mesh whose scratch cannot fit returns CPR_ENOMEM with a
+    NULL context and releases what it had allocated: once for a state far
+    beyond the GPU (P=4 on 23170^2, 429 GB per state), once where the first
+    two stage buffers fit and the third does not. Device free memory is the
+    same afterwards, and a small context can still be made."""
+    from ctypes import byref, c_void_p
+    from paper_1709_01619_amd import _lib
+    t = torch()
+    lib = _lib.load()
+    t.cuda.synchronize()
+    free0, total = t.cuda.mem_get_info()
+    # P=4: 800 bytes per element per state; four states of this size
+    n_partial = int(math.sqrt(0.4 * free0 / 800.0))
+    for n in (23170, n_partial):
+        say("init out of memory", n)
+        cfg = _lib.make_config(4, n, n)
+        ctx = c_void_p(12345)
+        st = lib.cpr_init(byref(cfg), None, byref(ctx))
+        assert st == _lib.CPR_ENOMEM, (n, st)
+        assert not ctx.value
+        t.cuda.synchronize()
+        free1, _ = t.cuda.mem_get_info()
+        assert abs(free1 - free0) <= 64 << 20, (n, free0, free1)
+    s = make_solver(cpr.Grid(P=2, nx=8, ny=8))
+    q = inputs.random_state((8, 8, 3, 3), seed=1)
+    s.residual(dev(q))
+    s.sync()
