@@ -154,6 +154,174 @@ __device__ __forceinline__ void rusanov(const R qL[4], const R qR[4], R gam, R g
   bad = bad || nonphysical(qL[0], pL) || nonphysical(qR[0], pR);
 }
 
+// ---- Deviation form of the float32 residual ----
+// The float32 (FP32-bulk) residual rounds deviations from a reference state
+// instead of full flux values. Each element line takes its first solution
+// point q_r (float64) as reference; the line works with d = q - q_r, formed
+// in float64 and then rounded. The rows of D sum to zero and the
+// extrapolation rows to one, so D F = D (F - F(q_r)), and every face term
+// F_face - f_face is a difference of deviations once the Rusanov flux is
+// written in the same frame; F(q_r) itself is never formed. A neighbour's
+// face state enters a line's frame as its own-frame value plus the
+// difference of the two references (float64, then rounded). The flux
+// deviation dF = F(q_r + d) - F(q_r) is written with the product rule from
+// d and the reference's primitive values, so its rounding scales with d:
+//   du_n = (dm_n - u_n,r drho) / rho,
+//   dK = ((m_r + dm/2) . dm - K_r drho) / rho      (K = |m|^2 / (2 rho)),
+//   dp = (g-1)(dE - dK),
+//   dF = (dm_n, m_n,r du_n + dm_n u_n + dp, m_t,r du_n + dm_t u_n,
+//         du_n (E_r + p_r + dE + dp) + u_n,r (dE + dp)).
+// Everything is written in line-normal (n) and line-tangential (t) terms, so
+// the x and y sweeps round transposed data identically.
+template <typename R>
+struct DevRef {
+  R rho, mn, mt, un, ut, p, H, K;  // H = E + p, K = rho |V|^2 / 2 of the reference
+};
+
+// Reference constants for a line along AX from its reference state: the
+// float64 values rounded, and the primitive values formed from those in R.
+// Any consistent constants serve: F(q_r) itself never enters, and an error
+// in a constant only scales terms that are products with a deviation.
+template <int AX, typename R>
+__device__ __forceinline__ DevRef<R> dev_ref(const double r[4], R gm1) {
+  constexpr int NN = 1 + AX, TT = 2 - AX;
+  DevRef<R> c;
+  c.rho = (R)r[0];
+  c.mn = (R)r[NN];
+  c.mt = (R)r[TT];
+  const R E = (R)r[3];
+  const R ir = recip(c.rho);
+  c.un = c.mn * ir;
+  c.ut = c.mt * ir;
+  c.K = R(0.5) * r_fma(c.mn, c.un, c.mt * c.ut);
+  c.p = gm1 * (E - c.K);
+  c.H = E + c.p;
+  return c;
+}
+
+// Full-state values at deviation d from the reference: rho, 1/rho, u_n,
+// p, and the deviations du_n and dp the flux deviation uses. The kinetic
+// energy K = |m|^2 / (2 rho) changes by
+//   dK = ((m_r + dm/2) . dm - K_r drho) / rho,
+// which needs no tangential velocity.
+template <int AX, typename R>
+struct DevState {
+  R rho, ir, un, p, dun, dp;
+  __device__ __forceinline__ DevState(const R d[4], const DevRef<R>& c, R gm1) {
+    constexpr int NN = 1 + AX, TT = 2 - AX;
+    rho = c.rho + d[0];
+    ir = recip(rho);
+    dun = r_fma(-c.un, d[0], d[NN]) * ir;
+    un = c.un + dun;
+    const R mhn = r_fma(R(0.5), d[NN], c.mn), mht = r_fma(R(0.5), d[TT], c.mt);
+    const R dK = r_fma(-c.K, d[0], r_fma(mhn, d[NN], mht * d[TT])) * ir;
+    dp = gm1 * (d[3] - dK);
+    p = c.p + dp;
+  }
+};
+
+// dF = F(q_r + d) - F(q_r) for the flux along AX; also the state values.
+template <int AX, typename R>
+__device__ __forceinline__ DevState<AX, R> dev_flux(const R d[4], const DevRef<R>& c, R gm1,
+                                                    R F[4]) {
+  constexpr int NN = 1 + AX, TT = 2 - AX;
+  const DevState<AX, R> s(d, c, gm1);
+  const R dEp = d[3] + s.dp;
+  F[0] = d[NN];
+  F[NN] = r_fma(c.mn, s.dun, r_fma(d[NN], s.un, s.dp));
+  F[TT] = r_fma(c.mt, s.dun, d[TT] * s.un);
+  F[3] = r_fma(s.dun, c.H + dEp, c.un * dEp);
+  return s;
+}
+
+// Rusanov flux in a line's frame: both face states and the result are
+// deviations from that line's reference (F_hat - F(q_r)).
+template <int AX, typename R>
+__device__ __forceinline__ void rusanov_dev(const R dL[4], const R dR[4], const DevRef<R>& c,
+                                            R gam, R gm1, R Fh[4], bool& bad) {
+  R fL[4], fR[4];
+  const DevState<AX, R> sL = dev_flux<AX>(dL, c, gm1, fL);
+  const DevState<AX, R> sR = dev_flux<AX>(dR, c, gm1, fR);
+  const R lL = fabs(sL.un) + sqrt_pos(gam * sL.p * sL.ir);
+  const R lR = fabs(sR.un) + sqrt_pos(gam * sR.p * sR.ir);
+  const R lam = (lL >= lR) ? lL : lR;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Fh[k] = r_fma(-(R(0.5) * lam), dR[k] - dL[k], R(0.5) * (fL[k] + fR[k]));
+  bad = bad || nonphysical(sL.rho, sL.p) || nonphysical(sR.rho, sR.p);
+}
+
+// line_ops in deviation form: d the line's deviations; face states and
+// face fluxes come back in the line's frame.
+template <int N1, int AX, bool LOB, typename R>
+__device__ __forceinline__ void line_ops_dev(const R d[4][N1], const DevRef<R>& c,
+                                             const KTab<R, N1>& T, R gm1, R qlo[4], R qhi[4],
+                                             R flo[4], R fhi[4], R dF[4][N1], bool& bad) {
+  R F[4][N1];
+#pragma unroll
+  for (int n = 0; n < N1; ++n) {
+    R dp[4] = {d[0][n], d[1][n], d[2][n], d[3][n]};
+    R fp[4];
+    const DevState<AX, R> s = dev_flux<AX>(dp, c, gm1, fp);
+    bad = bad || nonphysical(s.rho, s.p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) F[k][n] = fp[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (LOB) {
+      qlo[k] = d[k][0];
+      qhi[k] = d[k][N1 - 1];
+      flo[k] = F[k][0];
+      fhi[k] = F[k][N1 - 1];
+    } else {
+      qlo[k] = dot_n<N1>([&](int n) { return T.em(n); }, d[k]);
+      qhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, d[k]);
+      flo[k] = dot_n<N1>([&](int n) { return T.em(n); }, F[k]);
+      fhi[k] = dot_n<N1>([&](int n) { return T.ep(n); }, F[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < N1; ++i) dF[k][i] = dot_n<N1>([&](int n) { return T.D(i, n); }, F[k]);
+  }
+}
+
+// line_ops_chain in deviation form: D q = D d, and the chain rule's
+// coefficients (velocity, pressure, E + p at each point) come from the
+// reference plus the deviation.
+template <int N1, int AX, typename R>
+__device__ __forceinline__ void line_ops_chain_dev(const R d[4][N1], const DevRef<R>& c,
+                                                   const KTab<R, N1>& T, R gm1, R qlo[4],
+                                                   R qhi[4], R flo[4], R fhi[4], R dF[4][N1],
+                                                   bool& bad) {
+  constexpr int NN = 1 + AX, TT = 2 - AX;
+#pragma unroll
+  for (int i = 0; i < N1; ++i) {
+    R dq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dq[k] = dot_n<N1>([&](int n) { return T.D(i, n); }, d[k]);
+    const R dp_[4] = {d[0][i], d[1][i], d[2][i], d[3][i]};
+    const DevState<AX, R> s(dp_, c, gm1);
+    bad = bad || nonphysical(s.rho, s.p);
+    const R ut = c.ut + r_fma(-c.ut, dp_[0], dp_[TT]) * s.ir;
+    const R mn = c.mn + dp_[NN], mt = c.mt + dp_[TT];
+    const R Ep = c.H + (dp_[3] + s.dp);
+    const R dun = r_fma(-s.un, dq[0], dq[NN]) * s.ir;
+    const R dp = gm1 * r_fma(R(0.5) * r_fma(s.un, s.un, ut * ut), dq[0],
+                             dq[3] - r_fma(s.un, dq[NN], ut * dq[TT]));
+    dF[0][i] = dq[NN];
+    dF[NN][i] = r_fma(mn, dun, r_fma(dq[NN], s.un, dp));
+    dF[TT][i] = r_fma(mt, dun, dq[TT] * s.un);
+    dF[3][i] = r_fma(Ep, dun, s.un * (dq[3] + dp));
+  }
+  R dlo[4], dhi[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    dlo[k] = qlo[k] = d[k][0];
+    dhi[k] = qhi[k] = d[k][N1 - 1];
+  }
+  (void)dev_flux<AX>(dlo, c, gm1, flo);
+  (void)dev_flux<AX>(dhi, c, gm1, fhi);
+}
+
 // Line operations on the N1 points of one element row (AX=0) or column
 // (AX=1): face states qlo (at -1) and qhi (at +1), the flux interpolant's
 // face values flo, fhi, and its derivative dF at the points. On Gauss points

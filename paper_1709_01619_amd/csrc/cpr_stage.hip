@@ -62,6 +62,8 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   constexpr int TPW = TilesPerGroup<N1, R>::value;
   constexpr bool LOB = SCH != kSchemeGlLp;      // Gauss-Lobatto points
   constexpr bool CHAIN = SCH == kSchemeGllChain;
+  // float32 residuals are formed in deviation form (cpr_device.h)
+  constexpr bool DEV = sizeof(R) == 4;
   constexpr int NT = 64 * N1;                   // lanes per tile
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;  // odd LDS stride per element
   constexpr int VS = 64 * S;                    // LDS stride per variable
@@ -105,6 +107,11 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   int hs = 0, hp = 0, hm = 0;
   bool hact = false, hout = false;
   R hq[4] = {R(0), R(0), R(0), R(0)};
+  // deviation form: the neighbour's face state is formed in the frame of
+  // the neighbour line's first point hr0 (the face point itself on
+  // Gauss-Lobatto points) and moved into the own line's frame once that
+  // line's reference is read from LDS
+  double hr0[4] = {0.0, 0.0, 0.0, 0.0};
 
   // ---- A: tile -> LDS (coalesced along each tile row of elements) and the
   // outside neighbour lines, all loads issued before any is consumed ----
@@ -196,13 +203,21 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
     }
     if (LOB && halo && hact && hout) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) hq[k] = (R)hraw[k][0];
+      for (int k = 0; k < 4; ++k) {
+        if (DEV)
+          hr0[k] = hraw[k][0];
+        else
+          hq[k] = (R)hraw[k][0];
+      }
     } else if (halo && hact && hout) {
       R ln[4][N1];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < 4; ++k) {
+        if (DEV) hr0[k] = hraw[k][0];
+        ln[k][0] = DEV ? R(0) : (R)hraw[k][0];
 #pragma unroll
-        for (int n = 0; n < N1; ++n) ln[k][n] = (R)hraw[k][n];
+        for (int n = 1; n < N1; ++n) ln[k][n] = (R)(hraw[k][n] - hr0[k]);
+      }
       // the neighbour's face that touches this tile
       const bool hi = (hs == 0 || hs == 2);
 #pragma unroll
@@ -225,17 +240,23 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       stride = N1;
     }
     const bool lo = (hs == 0 || hs == 2);
+    // own line's reference (deviation form): its first point
+    double ref[4] = {0.0, 0.0, 0.0, 0.0};
+    if (DEV) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) ref[k] = qs[k * VS + e * S + off];
+    }
     R qin[4];
     if (LOB) {
       const int n = lo ? 0 : N1 - 1;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) qin[k] = (R)qs[k * VS + e * S + off + n * stride];
+      for (int k = 0; k < 4; ++k) qin[k] = (R)(qs[k * VS + e * S + off + n * stride] - ref[k]);
     } else {
       R ln[4][N1];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int n = 0; n < N1; ++n) ln[k][n] = (R)qs[k * VS + e * S + off + n * stride];
+        for (int n = 0; n < N1; ++n) ln[k][n] = (R)(qs[k * VS + e * S + off + n * stride] - ref[k]);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         qin[k] = dot_n<N1>([&](int n) { return lo ? T.em(n) : T.ep(n); }, ln[k]);
@@ -243,6 +264,9 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
     if (!hout) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) hq[k] = qin[k];
+    } else if (DEV) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hq[k] = LOB ? (R)(hr0[k] - ref[k]) : (R)(hr0[k] - ref[k]) + hq[k];
     }
     const bool lo_side = (hs == 0 || hs == 2);  // neighbour is on the left/below
     R qL[4], qR[4], Fh[4];
@@ -251,10 +275,17 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
       qL[k] = lo_side ? hq[k] : qin[k];
       qR[k] = lo_side ? qin[k] : hq[k];
     }
-    if (hs < 2)
-      rusanov<0>(qL, qR, gam, gm1, Fh, bad);
-    else
-      rusanov<1>(qL, qR, gam, gm1, Fh, bad);
+    if constexpr (DEV) {
+      if (hs < 2)
+        rusanov_dev<0>(qL, qR, dev_ref<0, R>(ref, gm1), gam, gm1, Fh, bad);
+      else
+        rusanov_dev<1>(qL, qR, dev_ref<1, R>(ref, gm1), gam, gm1, Fh, bad);
+    } else {
+      if (hs < 2)
+        rusanov<0>(qL, qR, gam, gm1, Fh, bad);
+      else
+        rusanov<1>(qL, qR, gam, gm1, Fh, bad);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) hF[hs][hp][hm][k] = Fh[k];
   }
@@ -269,10 +300,27 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   const bool actX = cxX < nax && cyX < nay;
   const bool actY = cxY < nax && cyY < nay;
   R qcol[4][N1];
+  // deviation form: the column's reference (its first point), and the
+  // differences to the references of the columns below and above, whose
+  // face state and face flux enter this column's frame (lanes at the tile
+  // edge read a clamped, unused element: their faces come from hF)
+  double rc[4] = {0.0, 0.0, 0.0, 0.0};
+  R dbel[4], dabv[4];
+  if constexpr (DEV) {
+    const int eb = eY >= kTile ? eY - kTile : eY, ea = eY < 64 - kTile ? eY + kTile : eY;
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
+      rc[k] = qs[k * VS + eY * S + wv];
+      dbel[k] = (R)(qs[k * VS + eb * S + wv] - rc[k]);
+      dabv[k] = (R)(qs[k * VS + ea * S + wv] - rc[k]);
+    }
+  }
 #pragma unroll
-    for (int n = 0; n < N1; ++n) qcol[k][n] = (R)qs[k * VS + eY * S + n * N1 + wv];
+  for (int k = 0; k < 4; ++k) {
+    qcol[k][0] = DEV ? R(0) : (R)qs[k * VS + eY * S + wv];
+#pragma unroll
+    for (int n = 1; n < N1; ++n) qcol[k][n] = (R)(qs[k * VS + eY * S + n * N1 + wv] - rc[k]);
+  }
   __syncthreads();  // tile-boundary fluxes are in hF
 
   const double dt = (A.dt_dev != nullptr) ? *A.dt_dev : A.dt;
@@ -282,21 +330,46 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   {
     R qlo[4], qhi[4], flo[4], fhi[4], dF[4][N1];
     bool b1 = false, b2 = false;
-    if constexpr (CHAIN)
-      line_ops_chain<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
-    else
-      line_ops<N1, 1, LOB>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     R qnb[4], Fs[4], Fn[4];
+    if constexpr (DEV) {
+      const DevRef<R> c = dev_ref<1, R>(rc, gm1);
+      if constexpr (CHAIN)
+        line_ops_chain_dev<N1, 1>(qcol, c, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+      else
+        line_ops_dev<N1, 1, LOB>(qcol, c, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+      // the element below: its face state moves into this frame by the
+      // difference of the references; the face flux the element above forms
+      // in its frame moves into this one by the flux deviation of theirs
 #pragma unroll
-    for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], kTile, 64);
-    rusanov<1>(qnb, qlo, gam, gm1, Fs, b2);
-    if (cyY == 0) {
+      for (int k = 0; k < 4; ++k) qnb[k] = dbel[k] + __shfl_up(qhi[k], kTile, 64);
+      rusanov_dev<1>(qnb, qlo, c, gam, gm1, Fs, b2);
+      if (cyY == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) Fs[k] = hF[2][cxY][wv][k];
-      b2 = false;
+        for (int k = 0; k < 4; ++k) Fs[k] = hF[2][cxY][wv][k];
+        b2 = false;
+      }
+      R fa[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fn[k] = __shfl_down(Fs[k], kTile, 64);
+      (void)dev_flux<1>(dabv, c, gm1, fa);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fn[k] = Fn[k] + fa[k];
+    } else {
+      if constexpr (CHAIN)
+        line_ops_chain<N1, 1>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+      else
+        line_ops<N1, 1, LOB>(qcol, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], kTile, 64);
+      rusanov<1>(qnb, qlo, gam, gm1, Fs, b2);
+      if (cyY == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Fs[k] = hF[2][cxY][wv][k];
+        b2 = false;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fn[k] = __shfl_down(Fs[k], kTile, 64);
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Fn[k] = __shfl_down(Fs[k], kTile, 64);
     if (cyY == nay - 1) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) Fn[k] = hF[3][cxY][wv][k];
@@ -315,6 +388,17 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int n = 0; n < N1; ++n) qrow[k][n] = qs[k * VS + eX * S + wv * N1 + n];
+  // deviation form: differences of the west and east rows' references to
+  // this row's (clamped, unused elements at the tile edge)
+  R dwst[4], deas[4];
+  if constexpr (DEV) {
+    const int ew = eX > 0 ? eX - 1 : eX, ee = eX < 63 ? eX + 1 : eX;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      dwst[k] = (R)(qs[k * VS + ew * S + wv * N1] - qrow[k][0]);
+      deas[k] = (R)(qs[k * VS + ee * S + wv * N1] - qrow[k][0]);
+    }
+  }
   __syncthreads();  // every row has been read
 #pragma unroll
   for (int k = 0; k < 4; ++k)
@@ -326,26 +410,54 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   {
     R qr[4][N1];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k) {
+      // deviation form: the row's first point is its reference
+      qr[k][0] = DEV ? R(0) : (R)qrow[k][0];
 #pragma unroll
-      for (int n = 0; n < N1; ++n) qr[k][n] = (R)qrow[k][n];
+      for (int n = 1; n < N1; ++n) qr[k][n] = (R)(qrow[k][n] - (DEV ? qrow[k][0] : 0.0));
+    }
     R qlo[4], qhi[4], flo[4], fhi[4], dF[4][N1];
     bool b1 = false, b2 = false;
-    if constexpr (CHAIN)
-      line_ops_chain<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
-    else
-      line_ops<N1, 0, LOB>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
     R qnb[4], Fw[4], Fe[4];
+    if constexpr (DEV) {
+      double rr[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], 1, 64);
-    rusanov<0>(qnb, qlo, gam, gm1, Fw, b2);
-    if (cxX == 0) {
+      for (int k = 0; k < 4; ++k) rr[k] = qrow[k][0];
+      const DevRef<R> c = dev_ref<0, R>(rr, gm1);
+      if constexpr (CHAIN)
+        line_ops_chain_dev<N1, 0>(qr, c, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+      else
+        line_ops_dev<N1, 0, LOB>(qr, c, T, gm1, qlo, qhi, flo, fhi, dF, b1);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) Fw[k] = hF[0][cyX][wv][k];
-      b2 = false;
+      for (int k = 0; k < 4; ++k) qnb[k] = dwst[k] + __shfl_up(qhi[k], 1, 64);
+      rusanov_dev<0>(qnb, qlo, c, gam, gm1, Fw, b2);
+      if (cxX == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Fw[k] = hF[0][cyX][wv][k];
+        b2 = false;
+      }
+      R fa[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fe[k] = __shfl_down(Fw[k], 1, 64);
+      (void)dev_flux<0>(deas, c, gm1, fa);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fe[k] = Fe[k] + fa[k];
+    } else {
+      if constexpr (CHAIN)
+        line_ops_chain<N1, 0>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+      else
+        line_ops<N1, 0, LOB>(qr, T, gm1, qlo, qhi, flo, fhi, dF, b1);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) qnb[k] = __shfl_up(qhi[k], 1, 64);
+      rusanov<0>(qnb, qlo, gam, gm1, Fw, b2);
+      if (cxX == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Fw[k] = hF[0][cyX][wv][k];
+        b2 = false;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Fe[k] = __shfl_down(Fw[k], 1, 64);
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Fe[k] = __shfl_down(Fw[k], 1, 64);
     if (cxX == nax - 1) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) Fe[k] = hF[1][cyX][wv][k];
