@@ -272,6 +272,20 @@ def test_adjoint_step_fp32_bulk(P, monkeypatch):
     bound = 2 * dt * 64 * 2.0 ** -24 * scale
     print(f"fp32_bulk adjoint step P={P}: max err {err:.3e}, bound {bound:.3e}")
     assert err <= bound
+    # against the unmodified oracle (ties to 1e-12): the difference adds the
+    # tie rule's own effect, 1/2 |jump| |grad lam_L - grad lam_R| per face on
+    # the faces whose speeds differ by less than 2^-17 but more than 1e-12;
+    # that term is measured as the difference of the oracle under the two
+    # thresholds
+    monkeypatch.setattr(adjoint, "TIE_REL", 1e-12)
+    lam2 = (2.0 / 3.0) * (lam + dt * adjoint.residual_vjp(q2, lam, g))
+    lam1 = 0.25 * (lam2 + dt * adjoint.residual_vjp(q1, lam2, g))
+    ref12 = lam1 + dt * adjoint.residual_vjp(q, lam1, g) + lam / 3.0 + 0.75 * lam2
+    tie = np.max(np.abs(ref - ref12))
+    err12 = np.max(np.abs(out - ref12))
+    print(f"fp32_bulk adjoint step P={P} vs the 1e-12 tie rule: max err {err12:.3e} "
+          f"({err12 / np.max(np.abs(ref12)):.2e} relative), tie-rule term {tie:.3e}")
+    assert err12 <= bound + tie
 
 
 def test_rollout_gradient_fp32_bulk():

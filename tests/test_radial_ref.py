@@ -129,3 +129,14 @@ def test_self_convergence():
     for (rc_a, rho_a, _, _), (rc_b, rho_b, _, _) in zip(sols[:-1], sols[1:]):
         d.append(np.mean(np.abs(rr.density_at(rc_b, rc_a, rho_a) - rho_b)) * 1.2)
     assert d[1] < 0.7 * d[0], d
+
+
+def test_stored_profile_is_the_reference():
+    """tests/golden/radial_profile_t025.txt (read by the benchmark) holds
+    this reference at t = 0.25, as make_radial_profile.py writes it."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "radial_profile_t025.txt")
+    r, rho = np.loadtxt(path, unpack=True)
+    rc, rho_ref = rr.solve(0.25, n=4000)[:2]
+    assert np.allclose(r, rc, atol=1e-6)
+    assert np.allclose(rho, rho_ref, rtol=1e-9, atol=1e-12)
