@@ -408,8 +408,8 @@ __device__ __forceinline__ void line_ops_chain(const R q[4][N1], const KTab<R, N
 
 // Coalesced copy between one tile of a state (4 variables x kTile element
 // rows, each a contiguous run of nax*NSP float64 in global memory) and its
-// LDS image (element stride S). The 4*kTile runs are dealt to the N1 waves
-// of the workgroup (wave w takes runs w, w+N1, ...); within a run, lane l
+// LDS image (element stride S). The 4*kTile runs are dealt to the NW waves
+// of the workgroup (wave w takes runs w, w+NW, ...); within a run, lane l
 // of pass it handles value it*64+l. All loads of a wave are issued before
 // any of them is consumed, so one memory round trip covers the whole copy.
 // With runs of at least 64 values (PAIRS), 16-byte aligned states and even
@@ -417,12 +417,12 @@ __device__ __forceinline__ void line_ops_chain(const R q[4][N1], const KTab<R, N
 // (pass it, lane l: values 2(it*64+l) and the next), which halves the
 // memory instructions. With an odd number of points per element the two
 // may lie in neighbouring elements, so each has its own LDS slot.
-template <int N1, int S>
+template <int N1, int S, int NW = N1>
 struct TileCopy {
   static constexpr int NSP = N1 * N1;
   static constexpr int SEG = kTile * NSP;          // values in a full run
   static constexpr int NIT = (SEG + 63) / 64;      // passes per run
-  static constexpr int NRUN = (4 * kTile + N1 - 1) / N1;  // runs per wave
+  static constexpr int NRUN = (4 * kTile + NW - 1) / NW;  // runs per wave (NW waves)
   // pairs where a run holds at least 64 values (P >= 2); at P = 1 they
   // would leave most lanes idle and cost registers
   static constexpr bool PAIRS = SEG >= 64;
@@ -447,7 +447,7 @@ struct TileCopy {
     }
   }
   // run u of wave wv: variable k, tile row cy; valid when sg < 4*kTile.
-  __device__ __forceinline__ static int run(int wv, int u) { return wv + N1 * u; }
+  __device__ __forceinline__ static int run(int wv, int u) { return wv + NW * u; }
 };
 
 // XCD-aware tile order: consecutive dispatch slots go round-robin over the

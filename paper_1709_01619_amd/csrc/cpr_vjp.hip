@@ -228,11 +228,111 @@ __device__ __forceinline__ void line_adj_finish_chain(const R q[4][N1], const Li
   }
 }
 
+// One sweep of the transpose along AX for the split layout: the line of
+// every element this wave owns (point n of variable k at
+// k * VS + base + n * step in the q and v images) is read for its face
+// terms, the interior faces are finished with the neighbours by wave
+// shuffles (shift lanes apart; hlo / hhi the tile-boundary face-state
+// cotangents where at_lo / at_hi), and the line is read again for the
+// interior transpose, whose values go to emit(k, n, value).
+template <int N1, int AX, bool CHAIN, typename R, typename LT, typename Emit>
+__device__ __forceinline__ void adj_sweep_split(const LT* qs, const LT* vs, int VS, int base,
+                                                int step, const KTab<R, N1>& T, R rd, R gam,
+                                                int shift, bool at_lo, bool at_hi, const R* hlo,
+                                                const R* hhi, bool act, bool& bad, Emit emit) {
+  R qlo[4], qhi[4], slo[4], shi[4];
+  {
+    R q[4][N1], v[4][N1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int n = 0; n < N1; ++n) {
+        q[k][n] = (R)qs[k * VS + base + n * step];
+        v[k][n] = (R)vs[k * VS + base + n * step];
+      }
+    LineAdj<N1, AX, R> L;
+    line_adj_prep<N1, AX>(q, v, T, rd, L);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      qlo[k] = L.qlo[k];
+      qhi[k] = L.qhi[k];
+      slo[k] = L.slo[k];
+      shi[k] = L.shi[k];
+    }
+  }
+  // the line is read again below rather than kept across the Rusanov
+  // transpose
+  asm volatile("" ::: "memory");
+  R qnb[4], s[4], cL[4], cR[4], clo[4], chi[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    qnb[k] = __shfl_up(qhi[k], shift, 64);
+    s[k] = slo[k] + __shfl_up(shi[k], shift, 64);
+  }
+  bool b2 = false;
+  rusanov_vjp<AX>(qnb, qlo, s, gam, cL, cR, b2);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    clo[k] = cR[k];
+    chi[k] = __shfl_down(cL[k], shift, 64);
+  }
+  if (at_lo) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) clo[k] = hlo[k];
+    b2 = false;
+  }
+  if (at_hi) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) chi[k] = hhi[k];
+  }
+  if (act) bad = bad || b2;
+  R q[4][N1], v[4][N1], out[4][N1];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) {
+      q[k][n] = (R)qs[k * VS + base + n * step];
+      v[k][n] = (R)vs[k * VS + base + n * step];
+    }
+  LineAdj<N1, AX, R> L;
+  line_adj_prep<N1, AX>(q, v, T, rd, L);
+  if constexpr (CHAIN)
+    line_adj_finish_chain<N1, AX>(q, L, clo, chi, T, gam, out);
+  else
+    line_adj_finish<N1, AX>(q, L, clo, chi, T, gam, out);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int n = 0; n < N1; ++n) emit(k, n, out[k][n]);
+}
+
+// Third-image layout with concurrent sweeps: P=4 in float64 with the flux
+// derivative (see the kernel); the chain rule's dual-number transpose needs
+// more registers than three waves per SIMD leave.
 template <int P, typename R, bool CHAIN>
-__global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P + 1> T, VjpArgs A) {
+struct VjpSplit {
+  static constexpr bool value = sizeof(R) == 8 && P == 4 && !CHAIN;
+};
+
+template <int P, typename R, bool CHAIN>
+__global__ __launch_bounds__((64 * (VjpSplit<P, R, CHAIN>::value ? 2 * (P + 1) : P + 1)),
+                             (VjpSplit<P, R, CHAIN>::value ? 3 : 1)) void vjp_kernel(
+    Geometry G, KTab<R, P + 1> T, VjpArgs A) {
   constexpr int N1 = P + 1;
   constexpr int NSP = N1 * N1;
   constexpr int S = (NSP & 1) ? NSP : NSP + 1;
+  // P=4 in float64 (split layout): the q and v images of a tile take
+  // 105 KB, so a CU holds one workgroup either way. A third image takes the
+  // column results (155 KB in all), which lets the column sweep (the first
+  // P+1 waves) and the row sweep (the next P+1) run at the same time, neither
+  // overwriting an image the other reads; each sweep reads its line twice
+  // from LDS (face terms, then interior) rather than holding it across the
+  // Rusanov transpose, which keeps the registers within three waves per
+  // SIMD. (Half-height tiles with two lines per wave, two workgroups per CU,
+  // measured 1.75 ms per launch against 1.20 ms for this layout at P=4
+  // 1024^2: twice the tile-boundary work and register spills.)
+  constexpr bool OIMG = VjpSplit<P, R, CHAIN>::value;
+  constexpr int NW = OIMG ? 2 * N1 : N1;  // waves per workgroup
   constexpr int VS = 64 * S;
   // LDS images in the compute type: float64 states are rounded to float32
   // here in FP32-bulk, as the line algebra does anyway
@@ -240,7 +340,10 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
   constexpr bool F32 = sizeof(R) == 4;
   __shared__ LT qs[4 * VS];
   __shared__ LT vs[4 * VS];
-  __shared__ R hC[4][kTile][N1][4];  // inside face-state cotangents at tile boundaries
+  // inside face-state cotangents at tile boundaries: W, E and S, N
+  __shared__ R hCx[2][kTile][N1][4];
+  __shared__ R hCy[2][kTile][N1][4];
+  __shared__ LT os_img[OIMG ? 4 * VS : 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -256,7 +359,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
 
   // tile of q and of v -> LDS; each wave issues all its loads of an array
   // before writing any of them
-  using TC = TileCopy<N1, S>;
+  using TC = TileCopy<N1, S, NW>;
   const TC tc(lane);
   const int seg_len = nax * NSP;
   // paired 16-byte copies of q, v, x, y and out (float64 states in both
@@ -415,7 +518,10 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
     for (int k = 0; k < 4; ++k) {
       // transmissive: both face states are the inside state
       cin[k] = !hout ? cL[k] + cR[k] : (lo_side ? cR[k] : cL[k]);
-      hC[hs][hp][hm][k] = cin[k];
+      if (hs < 2)
+        hCx[hs][hp][hm][k] = cin[k];
+      else
+        hCy[hs - 2][hp][hm][k] = cin[k];
     }
   }
 
@@ -425,6 +531,28 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
   const int cxY = lane & 7, cyY = lane >> 3, eY = lane;
   const bool actX = cxX < nax && cyX < nay;
   const bool actY = cxY < nax && cyY < nay;
+  LT* const oimg = OIMG ? os_img : qs;
+
+  if constexpr (OIMG) {
+    __syncthreads();  // images and tile-boundary cotangents are in LDS
+    const int grp = wv >= N1 ? 1 : 0;  // wave-uniform: 0 column sweep, 1 row sweep
+    const int ln = wv - grp * N1;       // the line of every element this wave takes
+    const int el = lane, cx = lane & 7, cy = lane >> 3;
+    const bool act = cx < nax && cy < nay;
+    if (grp == 0)
+      adj_sweep_split<N1, 1, CHAIN>(qs, vs, VS, el * S + ln, N1, T, rdy, gam, kTile, cy == 0,
+                                    cy == nay - 1, hCy[0][cx][ln], hCy[1][cx][ln], act, bad,
+                                    [&](int k, int n, R v) { os_img[k * VS + el * S + n * N1 + ln] = v; });
+    __syncthreads();  // every column result is in the third image
+    if (grp == 1)
+      adj_sweep_split<N1, 0, CHAIN>(qs, vs, VS, el * S + ln * N1, 1, T, rdx, gam, 1, cx == 0,
+                                    cx == nax - 1, hCx[0][cy][ln], hCx[1][cy][ln], act, bad,
+                                    [&](int k, int n, R v) {
+                                      // each row lane combines its own points
+                                      const int a = k * VS + el * S + ln * N1 + n;
+                                      os_img[a] = A.alpha * vs[a] + A.delta * ((double)v + os_img[a]);
+                                    });
+  } else {
   // Each sweep holds only its own line: the column sweep's result stays in
   // registers until every lane has read its row, then replaces q in LDS.
   R qcol[4][N1], vcol[4][N1];
@@ -458,12 +586,12 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
     }
     if (cyY == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) clo[k] = hC[2][cxY][wv][k];
+      for (int k = 0; k < 4; ++k) clo[k] = hCy[0][cxY][wv][k];
       b2 = false;
     }
     if (cyY == nay - 1) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) chi[k] = hC[3][cxY][wv][k];
+      for (int k = 0; k < 4; ++k) chi[k] = hCy[1][cxY][wv][k];
     }
     if constexpr (CHAIN)
       line_adj_finish_chain<N1, 1>(qcol, L, clo, chi, T, gam, oc);
@@ -472,17 +600,13 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
     if (actY) bad = bad || b2;
   }
 
-  R qrow[4][N1];
-  // float64 in FP64 contexts, where the combination alpha v below uses it;
-  // FP32-bulk adds alpha v from the float64 state in the epilogue instead
-  using VT = typename std::conditional<F32, R, double>::type;
-  VT vrow[4][N1];
+  R qrow[4][N1], vrow[4][N1];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
     for (int n = 0; n < N1; ++n) {
       qrow[k][n] = (R)qs[k * VS + eX * S + wv * N1 + n];
-      vrow[k][n] = vs[k * VS + eX * S + wv * N1 + n];
+      vrow[k][n] = (R)vs[k * VS + eX * S + wv * N1 + n];
     }
   __syncthreads();  // every row has been read
 #pragma unroll
@@ -494,12 +618,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
   R orow[4][N1];
   {
     LineAdj<N1, 0, R> L;
-    R vr[4][N1];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int n = 0; n < N1; ++n) vr[k][n] = (R)vrow[k][n];
-    line_adj_prep<N1, 0>(qrow, vr, T, rdx, L);
+    line_adj_prep<N1, 0>(qrow, vrow, T, rdx, L);
     R qnb[4], snb[4], s[4], cL[4], cR[4], clo[4], chi[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -516,12 +635,12 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
     }
     if (cxX == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) clo[k] = hC[0][cyX][wv][k];
+      for (int k = 0; k < 4; ++k) clo[k] = hCx[0][cyX][wv][k];
       b2 = false;
     }
     if (cxX == nax - 1) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) chi[k] = hC[1][cyX][wv][k];
+      for (int k = 0; k < 4; ++k) chi[k] = hCx[1][cyX][wv][k];
     }
     if constexpr (CHAIN)
       line_adj_finish_chain<N1, 0>(qrow, L, clo, chi, T, gam, orow);
@@ -539,10 +658,12 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
       if constexpr (F32) {
         qs[a] = orow[k][n] + qs[a];  // J^T v; alpha v and delta follow in float64
       } else {
+        // the v image is intact (the column results replaced the q image)
         const double jt = (double)orow[k][n] + qs[a];
-        qs[a] = A.alpha * vrow[k][n] + A.delta * jt;
+        qs[a] = A.alpha * vs[a] + A.delta * jt;
       }
     }
+  }
   __syncthreads();
 
   if constexpr (F32) {
@@ -690,7 +811,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
         const int sg = TC::run(wv, u);
         const int k = sg >> 3, cy = sg & 7;
         const bool ok = sg < 4 * kTile && cy < nay;
-        const double* img = qs + k * VS + cy * kTile * S;
+        const double* img = oimg + k * VS + cy * kTile * S;
   #pragma unroll
         for (int it = 0; it < TC::NIT2; ++it) {
           const int f = 2 * (it * 64 + lane);
@@ -744,7 +865,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void vjp_kernel(Geometry G, KTab<R, P
         const int sg = TC::run(wv, u);
         const int k = sg >> 3, cy = sg & 7;
         const bool ok = sg < 4 * kTile && cy < nay;
-        const double* img = qs + k * VS + cy * kTile * S;
+        const double* img = oimg + k * VS + cy * kTile * S;
   #pragma unroll
         for (int it = 0; it < TC::NIT; ++it) {
           const int f = it * 64 + lane;
@@ -778,11 +899,16 @@ template <int P, typename R>
 static hipError_t launch_vjp_t(const Geometry& g, const Tables1D& T, const VjpArgs& a,
                                bool chain, hipStream_t s) {
   const KTab<R, P + 1> kt = make_ktab<R, P + 1>(T, g);
-  const dim3 grid(g.ntx * g.nty), block(64 * (P + 1));
+  // the split layout (VjpSplit) runs both sweeps at once on 2 (P+1) waves;
+  // the plain one runs them in turn on P+1 waves
+  const auto launch = [&](auto kernel, bool split) {
+    hipLaunchKernelGGL(kernel, dim3(g.ntx * g.nty), dim3(64 * (split ? 2 * (P + 1) : P + 1)), 0, s,
+                       g, kt, a);
+  };
   if (chain)
-    hipLaunchKernelGGL((vjp_kernel<P, R, true>), grid, block, 0, s, g, kt, a);
+    launch(vjp_kernel<P, R, true>, VjpSplit<P, R, true>::value);
   else
-    hipLaunchKernelGGL((vjp_kernel<P, R, false>), grid, block, 0, s, g, kt, a);
+    launch(vjp_kernel<P, R, false>, VjpSplit<P, R, false>::value);
   return hipGetLastError();
 }
 
