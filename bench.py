@@ -19,7 +19,7 @@ Printed: one JSON line (rank 0). Extra objects:
   roofline      the stage kernel against HBM bandwidth (algorithmic bytes:
                 64 B per unknown per step = 21.33 B per unknown per launch)
   cpu_baseline  the CPU oracle timed on a bounded sample of the workload
-  fp32_bulk, l2_error, adjoint, scale_p4_1024, c1_small, c3_limited_riemann,
+  fp32_bulk, l2_error, adjoint, scale_p4_1024, scale_p3_1024, c1_small, c3_limited_riemann,
   c5_adjoint: see the keys.
   paper_cpr_gll_chain  the paper's own CPR scheme (Gauss-Lobatto points,
                 chain-rule divergence): stage timings, and the paper's
@@ -712,7 +712,8 @@ def main(argv=None):
                 "traffic": traffic,
                 "kernel": "cpr::stage_kernel<3,double,0,0>",
                 "note": "256^2 P=3 states are 33.6 MB each, so the three live states fit the "
-                        "256 MB Infinity Cache; see scale_p4_1024 for an HBM-resident case"}
+                        "256 MB Infinity Cache; scale_p3_1024 (the same kernel on 1024^2) and "
+                        "scale_p4_1024 are HBM-resident"}
 
     # ---- L2 error at t=10 (one period), FP64 vs FP32-bulk, and each
     # precision's rate on each mesh; the FP32-bulk rate counts only where
@@ -817,23 +818,30 @@ def main(argv=None):
                 adj["fp32_bulk"] = r
             log("adjoint", prec, r)
             del s
-    # ---- scale: P=4 1024^2 (104.9M unknowns), FP64 and FP32-bulk ----
-    scale = None
-    if not a.quick:
-        scale = {}
+    # ---- HBM-resident meshes: P=4 1024^2 (104.9M unknowns, 839 MB per
+    # state) and the headline's P=3 kernel on 1024^2 (67.1M unknowns, 537 MB
+    # per state), FP64 and FP32-bulk, launched kernel by kernel ----
+    def scale_case(P):
+        out = {}
         for prec in ("fp64", "fp32_bulk"):
-            s = Solver(4, 1024, 1024, precision=prec)
+            s = Solver(P, 1024, 1024, precision=prec)
             q = vortex_state(s)
             ms = time_steps(s, q, 1e-4, 20, 3)
             s.sync()
-            U4 = s.n_unknowns
-            ach = BYTES_PER_UNKNOWN_STEP / 3.0 * U4 / (ms * 1e-3 / 3.0) / 1e9
-            scale[prec] = {"ms_per_step": ms, "dof_updates_per_s": 3.0 * U4 / (ms * 1e-3),
-                           "roofline": {"bound": "hbm", "achieved": round(ach, 1),
-                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                        "frac": round(ach / HBM_PEAK_GBS, 4)}}
-            log("p4 1024", prec, scale[prec])
+            Us = s.n_unknowns
+            ach = BYTES_PER_UNKNOWN_STEP / 3.0 * Us / (ms * 1e-3 / 3.0) / 1e9
+            out[prec] = {"ms_per_step": ms, "dof_updates_per_s": 3.0 * Us / (ms * 1e-3),
+                         "roofline": {"bound": "hbm", "achieved": round(ach, 1),
+                                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                      "frac": round(ach / HBM_PEAK_GBS, 4)}}
+            log(f"p{P} 1024", prec, out[prec])
             del s, q
+        return out
+
+    scale = scale_p3 = None
+    if not a.quick:
+        scale = scale_case(4)
+        scale_p3 = scale_case(3)
 
     extra = {}
     if not a.quick:
@@ -908,6 +916,7 @@ def main(argv=None):
         "l2_error_t10": l2,
         "adjoint": adj,
         "scale_p4_1024": scale,
+        "scale_p3_1024": scale_p3,
         **extra,
     }
     print(json.dumps(line), flush=True)

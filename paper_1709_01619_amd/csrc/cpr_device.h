@@ -450,12 +450,22 @@ struct TileCopy {
   __device__ __forceinline__ static int run(int wv, int u) { return wv + NW * u; }
 };
 
-// XCD-aware tile order: consecutive dispatch slots go round-robin over the
-// 8 XCDs; give each XCD a contiguous range of tiles (raster order, x
-// fastest) so the halo rows shared by neighbouring tiles stay in one L2.
-__device__ __forceinline__ int xcd_tile(int bid, int ntiles) {
+// XCD-aware tile order. Consecutive dispatch slots go round-robin over the
+// 8 XCDs. When the row of ngx tile groups splits into 8 equal strips, XCD x
+// takes the strip of columns [x sw, (x+1) sw) and walks it row by row: a
+// tile's north and south neighbours then pass through the same L2 within a
+// row of the strip, and only the strips' side edges cross XCDs. Otherwise
+// each XCD takes a contiguous range of the ngx * ngy groups (raster order,
+// x fastest). Both maps are permutations of [0, ngx * ngy) for a grid of
+// exactly ngx * ngy workgroups.
+__device__ __forceinline__ int xcd_tile(int bid, int ngx, int ngy) {
   const int xcd = bid & 7, k = bid >> 3;
-  const int per = ntiles >> 3, rem = ntiles & 7;
+  if ((ngx & 7) == 0) {
+    const int sw = ngx >> 3;
+    return (k / sw) * ngx + xcd * sw + k % sw;
+  }
+  const int n = ngx * ngy;
+  const int per = n >> 3, rem = n & 7;
   return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
 

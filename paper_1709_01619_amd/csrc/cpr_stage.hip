@@ -78,7 +78,11 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int ntiles = G.ntx * G.nty;
-  const int tile = xcd_tile(blockIdx.x, (ntiles + TPW - 1) / TPW) * TPW + slot;
+  // groups of TPW tiles side by side in x: a grid of (ntx / TPW) x nty
+  // groups when TPW divides ntx, else one run of groups in raster order
+  const int tile = (G.ntx % TPW == 0 ? xcd_tile(blockIdx.x, G.ntx / TPW, G.nty)
+                                     : xcd_tile(blockIdx.x, (ntiles + TPW - 1) / TPW, 1)) *
+                       TPW + slot;
   const bool live = tile < ntiles;  // the last group's trailing slots may be empty
   const int tx = tile % G.ntx, ty = tile / G.ntx;
   const int I0 = tx * kTile, J0 = ty * kTile;

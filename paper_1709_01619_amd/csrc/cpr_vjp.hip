@@ -348,7 +348,7 @@ __global__ __launch_bounds__((64 * (VjpSplit<P, R, CHAIN>::value ? 2 * (P + 1) :
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int tile = xcd_tile(blockIdx.x, G.ntx * G.nty);
+  const int tile = xcd_tile(blockIdx.x, G.ntx, G.nty);
   const int tx = tile % G.ntx, ty = tile / G.ntx;
   const int I0 = tx * kTile, J0 = ty * kTile;
   const int nax = min(kTile, G.nx - I0), nay = min(kTile, G.ny - J0);
