@@ -328,9 +328,14 @@ __global__ __launch_bounds__((64 * (VjpSplit<P, R, CHAIN>::value ? 2 * (P + 1) :
   // overwriting an image the other reads; each sweep reads its line twice
   // from LDS (face terms, then interior) rather than holding it across the
   // Rusanov transpose, which keeps the registers within three waves per
-  // SIMD. (Half-height tiles with two lines per wave, two workgroups per CU,
-  // measured 1.75 ms per launch against 1.20 ms for this layout at P=4
-  // 1024^2: twice the tile-boundary work and register spills.)
+  // SIMD. Measured and not kept, at P=4 1024^2: half-height tiles with two
+  // lines per wave and two workgroups per CU (1.75 ms per launch against
+  // 1.20 ms: twice the tile-boundary work, and register spills); direct
+  // global-to-LDS copies of q and v (3 % slower than the register-staged
+  // pairs); and one workgroup per CU walking its share of the tiles with the
+  // next tile's copies in flight during the epilogue (5 % slower: its wait
+  // for the copies also waits for the last tile's stores, which a finished
+  // workgroup leaves to drain).
   constexpr bool OIMG = VjpSplit<P, R, CHAIN>::value;
   constexpr int NW = OIMG ? 2 * N1 : N1;  // waves per workgroup
   constexpr int VS = 64 * S;
@@ -539,19 +544,28 @@ __global__ __launch_bounds__((64 * (VjpSplit<P, R, CHAIN>::value ? 2 * (P + 1) :
     const int ln = wv - grp * N1;       // the line of every element this wave takes
     const int el = lane, cx = lane & 7, cy = lane >> 3;
     const bool act = cx < nax && cy < nay;
+    // the row sweep keeps its results in registers until the column
+    // results are in the third image, then each row lane combines its own
+    // points
+    R orow[4][N1];
     if (grp == 0)
       adj_sweep_split<N1, 1, CHAIN>(qs, vs, VS, el * S + ln, N1, T, rdy, gam, kTile, cy == 0,
                                     cy == nay - 1, hCy[0][cx][ln], hCy[1][cx][ln], act, bad,
                                     [&](int k, int n, R v) { os_img[k * VS + el * S + n * N1 + ln] = v; });
-    __syncthreads();  // every column result is in the third image
-    if (grp == 1)
+    else
       adj_sweep_split<N1, 0, CHAIN>(qs, vs, VS, el * S + ln * N1, 1, T, rdx, gam, 1, cx == 0,
                                     cx == nax - 1, hCx[0][cy][ln], hCx[1][cy][ln], act, bad,
-                                    [&](int k, int n, R v) {
-                                      // each row lane combines its own points
-                                      const int a = k * VS + el * S + ln * N1 + n;
-                                      os_img[a] = A.alpha * vs[a] + A.delta * ((double)v + os_img[a]);
-                                    });
+                                    [&](int k, int n, R v) { orow[k][n] = v; });
+    __syncthreads();  // every column result is in the third image
+    if (grp == 1) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int n = 0; n < N1; ++n) {
+          const int a = k * VS + el * S + ln * N1 + n;
+          os_img[a] = A.alpha * vs[a] + A.delta * ((double)orow[k][n] + os_img[a]);
+        }
+    }
   } else {
   // Each sweep holds only its own line: the column sweep's result stays in
   // registers until every lane has read its row, then replaces q in LDS.

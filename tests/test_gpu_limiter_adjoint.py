@@ -139,6 +139,43 @@ def test_adjoint_step_matches_oracle(P):
     assert np.max(np.abs(host(ld) - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("mesh", [(200, 176), (199, 170)], ids=lambda m: f"{m[0]}x{m[1]}")
+def test_residual_vjp_p4_large_meshes(mesh, bc):
+    """P=4 in float64 (the split-layout transpose) on 550 tiles, more than
+    the chip holds at once: nx even copies 16 bytes per lane into LDS, nx
+    odd 4 bytes and leaves a ragged tile column."""
+    nx, ny = mesh
+    g = cpr.Grid(P=4, nx=nx, ny=ny, x0=0.0, x1=2.0, y0=0.0, y1=1.5, bc=bc)
+    q = inputs.random_state((ny, nx, 5, 5), seed=6000 + nx)
+    v = np.random.default_rng(6100 + ny).standard_normal(g.shape)
+    say("vjp p4 large mesh", nx, ny, bc)
+    ref = adjoint.residual_vjp(q, v, g)
+    s = make_solver(g)
+    out = host(s.residual_vjp(dev(q), dev(v)))
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("nx", [130, 131])
+def test_adjoint_step_p4_large_meshes(nx):
+    """The three transposes of an adjoint step at P=4 on 289 tiles, the last
+    one with its two extra terms, also in place. A random state:
+    on the vortex's far field the two Rusanov speeds of a face agree to
+    about 1e-13, where the tie rule's threshold decides by rounding."""
+    g = cpr.Grid(P=4, nx=nx, ny=130, x0=0.0, x1=2.0, y0=0.0, y1=1.5)
+    q = inputs.random_state((130, nx, 5, 5), seed=6300 + nx)
+    lam = np.random.default_rng(6200 + nx).standard_normal(g.shape)
+    say("adjoint step p4 large mesh", nx)
+    dt = 1e-4
+    ref = adjoint.rk3_adjoint_step(q, dt, lam, g)
+    s = make_solver(g)
+    out = host(s.adjoint_step(dev(q), dt, dev(lam)))
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+    ld = dev(lam)
+    s.adjoint_step(dev(q), dt, ld, out=ld)
+    assert np.max(np.abs(host(ld) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
 def test_rollout_gradient_matches_oracle_and_fd():
     """Rollout with checkpointing (every 3 of 8 steps) on a perturbed P=3
     vortex: the gradient of 1/2 ||rho(T) - rho_exact||^2_w equals the
