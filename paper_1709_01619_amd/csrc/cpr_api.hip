@@ -28,13 +28,12 @@ struct cpr_ctx {
   double* lam1;    // adjoint stage cotangents
   double* lam2;
   double* qbar;    // element means (limiter)
-  int* iscr;       // [0] error flag, [1] skip flag, [2] troubled count, [4..5] lam bits,
-                   // [6..7] helper max bits, [8..9] troubled running total
+  int* iscr;       // [0] error flag, [1] skip flag, [2] troubled count,
+                   // [8..9] troubled running total
   double* dscal;   // [0] t, [1] dt
-  unsigned long long* lam_bits;
   unsigned long long* troubled_total;
-  double* partials;
-  double* red_out;  // 4 doubles
+  double* partials;  // per-block partial sums and wave-speed maxima
+  double* red_out;   // 4 doubles
   char last_error[512];
 };
 
@@ -287,7 +286,6 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
     delete x;
     return st;
   }
-  x->lam_bits = reinterpret_cast<unsigned long long*>(x->iscr + 4);
   x->troubled_total = reinterpret_cast<unsigned long long*>(x->iscr + 8);
   *out = x;
   return CPR_OK;
@@ -329,10 +327,11 @@ cpr_status cpr_rk3_step(cpr_ctx* ctx, double* q, double dt, int32_t apply_limite
       return CPR_EINVAL;
     }
     const double h = ctx->geo.dx < ctx->geo.dy ? ctx->geo.dx : ctx->geo.dy;
-    HIP_TRY(ctx, launch_max_wavespeed(ctx->cfg.order_p, ctx->geo, q, ctx->lam_bits, ctx->iscr,
+    HIP_TRY(ctx, launch_max_wavespeed(ctx->cfg.order_p, ctx->geo, q, ctx->partials, ctx->iscr,
                                       ctx->stream), "wave speed launch");
-    HIP_TRY(ctx, launch_cfl_dt(ctx->lam_bits, ctx->cfg.cfl, h, ctx->cfg.t_end, ctx->dscal,
-                               ctx->dscal + 1, ctx->iscr + 1, ctx->stream), "dt launch");
+    HIP_TRY(ctx, launch_cfl_dt(ctx->partials, wavespeed_parts(ctx->cfg.order_p, ctx->geo),
+                               ctx->cfg.cfl, h, ctx->cfg.t_end, ctx->dscal, ctx->dscal + 1,
+                               ctx->iscr + 1, ctx->stream), "dt launch");
   }
   cpr_status st;
   const bool lim = apply_limiter != 0;
@@ -445,15 +444,16 @@ cpr_status cpr_adjoint_step_stages(cpr_ctx* ctx, const double* q_n, const double
 
 cpr_status cpr_max_wavespeed(cpr_ctx* ctx, const double* q, double* out_host) {
   if (ctx == nullptr || q == nullptr || out_host == nullptr) return CPR_EINVAL;
-  unsigned long long* bits = reinterpret_cast<unsigned long long*>(ctx->iscr + 6);
-  HIP_TRY(ctx, launch_fill_int(ctx->iscr + 6, 0, 2, ctx->stream), "clear max");
-  HIP_TRY(ctx, launch_max_wavespeed(ctx->cfg.order_p, ctx->geo, q, bits, ctx->iscr, ctx->stream),
+  HIP_TRY(ctx, launch_max_wavespeed(ctx->cfg.order_p, ctx->geo, q, ctx->partials, ctx->iscr,
+                                    ctx->stream),
           "wave speed launch");
-  unsigned long long b = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(&b, bits, sizeof(b), hipMemcpyDeviceToHost, ctx->stream), "copy max");
+  HIP_TRY(ctx, launch_max_parts(ctx->partials, wavespeed_parts(ctx->cfg.order_p, ctx->geo),
+                                ctx->red_out, ctx->stream),
+          "wave speed maximum launch");
+  double v = 0.0;
+  HIP_TRY(ctx, hipMemcpyAsync(&v, ctx->red_out, sizeof(v), hipMemcpyDeviceToHost, ctx->stream),
+          "copy max");
   cpr_status st = check_device_error(ctx);
-  double v;
-  std::memcpy(&v, &b, sizeof(v));
   *out_host = v;
   return st;
 }

@@ -248,9 +248,12 @@ static int red_blocks(size_t npts) {
 
 size_t reduce_partials_size(int, const Geometry&) { return (size_t)kRedMaxBlocks * 4 + 8; }
 
+// Largest point wave speed |V| + c of each block's share of the points into
+// part[blockIdx.x] (one plain store per block: a thousand atomics on one
+// address would serialise at the L2), and the non-physical flag.
 template <int P>
 __global__ __launch_bounds__(kRedBlock) void wavespeed_kernel(Geometry G, const double* q,
-                                                              unsigned long long* bits, int* err) {
+                                                              double* part, int* err) {
   constexpr int NSP = (P + 1) * (P + 1);
   __shared__ double red[kRedBlock];
   const size_t npts = (size_t)G.nx * G.ny * NSP;
@@ -271,29 +274,46 @@ __global__ __launch_bounds__(kRedBlock) void wavespeed_kernel(Geometry G, const 
     if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicMax(bits, (unsigned long long)__double_as_longlong(red[0]));
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
   if (bad) atomicOr(err, 1);
 }
 
-hipError_t launch_max_wavespeed(int P, const Geometry& g, const double* q,
-                                unsigned long long* lam_bits, int* err, hipStream_t s) {
-  const size_t npts = (size_t)g.nx * g.ny * (P + 1) * (P + 1);
-  const dim3 grid(red_blocks(npts)), block(kRedBlock);
+int wavespeed_parts(int P, const Geometry& g) {
+  return red_blocks((size_t)g.nx * g.ny * (P + 1) * (P + 1));
+}
+
+hipError_t launch_max_wavespeed(int P, const Geometry& g, const double* q, double* part, int* err,
+                                hipStream_t s) {
+  const dim3 grid(wavespeed_parts(P, g)), block(kRedBlock);
   switch (P) {
-    case 1: hipLaunchKernelGGL((wavespeed_kernel<1>), grid, block, 0, s, g, q, lam_bits, err); break;
-    case 2: hipLaunchKernelGGL((wavespeed_kernel<2>), grid, block, 0, s, g, q, lam_bits, err); break;
-    case 3: hipLaunchKernelGGL((wavespeed_kernel<3>), grid, block, 0, s, g, q, lam_bits, err); break;
-    case 4: hipLaunchKernelGGL((wavespeed_kernel<4>), grid, block, 0, s, g, q, lam_bits, err); break;
+    case 1: hipLaunchKernelGGL((wavespeed_kernel<1>), grid, block, 0, s, g, q, part, err); break;
+    case 2: hipLaunchKernelGGL((wavespeed_kernel<2>), grid, block, 0, s, g, q, part, err); break;
+    case 3: hipLaunchKernelGGL((wavespeed_kernel<3>), grid, block, 0, s, g, q, part, err); break;
+    case 4: hipLaunchKernelGGL((wavespeed_kernel<4>), grid, block, 0, s, g, q, part, err); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-__global__ void cfl_dt_kernel(unsigned long long* bits, double cfl, double h, double t_end,
-                              double* t, double* dt, int* skip) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double lam = __longlong_as_double((long long)*bits);
-  *bits = 0ull;
+// the largest of part[0 .. n) (all >= 0), in one block of kRedBlock threads
+__device__ __forceinline__ double block_max_parts(const double* part, int n, double* red) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += kRedBlock) m = fmax(m, part[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kRedBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ __launch_bounds__(kRedBlock) void cfl_dt_kernel(const double* part, int nparts, double cfl,
+                                                           double h, double t_end, double* t,
+                                                           double* dt, int* skip) {
+  __shared__ double red[kRedBlock];
+  const double lam = block_max_parts(part, nparts, red);
+  if (threadIdx.x != 0) return;
   const double tn = *t;
   if (t_end > 0.0 && t_end - tn <= 1e-14 * t_end) {
     *skip = 1;
@@ -307,9 +327,22 @@ __global__ void cfl_dt_kernel(unsigned long long* bits, double cfl, double h, do
   *skip = 0;
 }
 
-hipError_t launch_cfl_dt(unsigned long long* lam_bits, double cfl, double h, double t_end,
+hipError_t launch_cfl_dt(const double* part, int nparts, double cfl, double h, double t_end,
                          double* t, double* dt, int* skip, hipStream_t s) {
-  hipLaunchKernelGGL(cfl_dt_kernel, dim3(1), dim3(64), 0, s, lam_bits, cfl, h, t_end, t, dt, skip);
+  hipLaunchKernelGGL(cfl_dt_kernel, dim3(1), dim3(kRedBlock), 0, s, part, nparts, cfl, h, t_end, t,
+                     dt, skip);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kRedBlock) void max_parts_kernel(const double* part, int nparts,
+                                                              double* out) {
+  __shared__ double red[kRedBlock];
+  const double m = block_max_parts(part, nparts, red);
+  if (threadIdx.x == 0) *out = m;
+}
+
+hipError_t launch_max_parts(const double* part, int nparts, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(max_parts_kernel, dim3(1), dim3(kRedBlock), 0, s, part, nparts, out);
   return hipGetLastError();
 }
 

@@ -101,12 +101,19 @@ hipError_t launch_limit(int P, const Geometry& g, const Tables1D& T, const Limit
 
 // Reductions. partials must hold reduce_partials_size() doubles.
 size_t reduce_partials_size(int P, const Geometry& g);
-hipError_t launch_max_wavespeed(int P, const Geometry& g, const double* q,
-                                unsigned long long* lam_bits, int* err, hipStream_t s);
-// dt = min(cfl h / lam, t_end - t); t += dt; skip when t >= t_end (t_end > 0).
-// Resets *lam_bits to 0 for the next use.
-hipError_t launch_cfl_dt(unsigned long long* lam_bits, double cfl, double h, double t_end,
+// The largest point wave speed |V| + c in two steps: launch_max_wavespeed
+// writes one maximum per block into part[0 .. wavespeed_parts(P, g)) (part
+// must hold that many doubles; reduce_partials_size() is enough), then
+// launch_cfl_dt or launch_max_parts takes their maximum.
+int wavespeed_parts(int P, const Geometry& g);
+hipError_t launch_max_wavespeed(int P, const Geometry& g, const double* q, double* part, int* err,
+                                hipStream_t s);
+// lam = max(part[0 .. nparts)); dt = min(cfl h / lam, t_end - t); t += dt;
+// skip when t >= t_end (t_end > 0).
+hipError_t launch_cfl_dt(const double* part, int nparts, double cfl, double h, double t_end,
                          double* t, double* dt, int* skip, hipStream_t s);
+// *out = max(part[0 .. nparts))
+hipError_t launch_max_parts(const double* part, int nparts, double* out, hipStream_t s);
 // Weighted sums: mode 0 -> out[0..3] = sum w_i w_j (dxdy/4) q_k;
 // mode 1 -> out[0] = sqrt(sum w w (dxdy/4) (a-b)^2 / area) for variable var.
 hipError_t launch_weighted_sum(int P, const Geometry& g, const Tables1D& T, int mode,
