@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 #include <new>
 
 #include "cpr.h"
@@ -28,10 +29,10 @@ struct cpr_ctx {
   double* lam1;    // adjoint stage cotangents
   double* lam2;
   double* qbar;    // element means (limiter)
-  int* iscr;       // [0] error flag, [1] skip flag, [2] troubled count,
-                   // [8..9] troubled running total
+  int* iscr;       // [0] error flag, [1] skip flag, [2] troubled count
   double* dscal;   // [0] t, [1] dt
-  unsigned long long* troubled_total;
+  unsigned long long* troubled_total;  // running total, one slot per limiter block
+  int n_total;                         // its slots
   double* partials;  // per-block partial sums and wave-speed maxima
   double* red_out;   // 4 doubles
   char last_error[512];
@@ -128,6 +129,7 @@ void free_all(cpr_ctx* c) {
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->iscr) (void)hipFree(c->iscr);
+  if (c->troubled_total) (void)hipFree(c->troubled_total);
 }
 
 // Read back the deferred device error flag (synchronising) and clear it.
@@ -276,6 +278,10 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
   if (e == hipSuccess) e = hipMalloc(&x->dscal, 4 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&x->partials, reduce_partials_size(c.order_p, x->geo) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&x->red_out, 4 * sizeof(double));
+  x->n_total = limit_blocks(x->geo);
+  if (e == hipSuccess) e = hipMalloc(&x->troubled_total, (size_t)x->n_total * sizeof(unsigned long long));
+  if (e == hipSuccess)
+    e = hipMemsetAsync(x->troubled_total, 0, (size_t)x->n_total * sizeof(unsigned long long), x->stream);
   if (e == hipSuccess) e = hipMemsetAsync(x->iscr, 0, 10 * sizeof(int), x->stream);
   if (e == hipSuccess) e = hipMemsetAsync(x->dscal, 0, 4 * sizeof(double), x->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
@@ -286,7 +292,6 @@ cpr_status cpr_init(const cpr_config* cfg, void* stream, cpr_ctx** out) {
     delete x;
     return st;
   }
-  x->troubled_total = reinterpret_cast<unsigned long long*>(x->iscr + 8);
   *out = x;
   return CPR_OK;
 }
@@ -506,12 +511,17 @@ cpr_status cpr_get_time(cpr_ctx* ctx, double* t_host, double* last_dt_host) {
 
 cpr_status cpr_troubled_total(cpr_ctx* ctx, int64_t* total_host, int32_t reset) {
   if (ctx == nullptr || total_host == nullptr) return CPR_EINVAL;
-  unsigned long long v = 0;
-  HIP_TRY(ctx, hipMemcpyAsync(&v, ctx->troubled_total, sizeof(v), hipMemcpyDeviceToHost, ctx->stream),
+  std::vector<unsigned long long> v((size_t)ctx->n_total);
+  HIP_TRY(ctx, hipMemcpyAsync(v.data(), ctx->troubled_total, v.size() * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, ctx->stream),
           "read troubled total");
-  if (reset) HIP_TRY(ctx, launch_fill_int(ctx->iscr + 8, 0, 2, ctx->stream), "clear troubled total");
+  if (reset)
+    HIP_TRY(ctx, launch_fill_int(reinterpret_cast<int*>(ctx->troubled_total), 0, 2 * v.size(), ctx->stream),
+            "clear troubled total");
   cpr_status st = check_device_error(ctx);
-  *total_host = (int64_t)v;
+  unsigned long long sum = 0;
+  for (unsigned long long b : v) sum += b;
+  *total_host = (int64_t)sum;
   return st;
 }
 

@@ -106,17 +106,19 @@ __device__ __forceinline__ void matvec(const double M[4][4], const double x[4], 
 }
 
 // ---------------------------------------------------- detect and limit --
+// Detection and limited slopes of element e: its mean qb, and slope[ax]
+// (d/dx, d/dy of the linear reconstruction) and troubled as the TVB
+// characteristic test decides. False when the mean density is not positive.
 template <int P>
-__global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, LimitArgs A) {
+__device__ __forceinline__ bool limit_element(const Geometry& G, const WTab<P + 1>& W,
+                                              const LimitArgs& A, int e, double qb[4],
+                                              double slope[2][4], bool& troubled) {
   constexpr int N1 = P + 1, NSP = N1 * N1;
-  if (A.skip != nullptr && *A.skip != 0) return;
-  const int ne = G.nx * G.ny;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
   const int I = e % G.nx, J = e / G.nx;
+  const int ne = G.nx * G.ny;
   const size_t plane = (size_t)ne * NSP;
 
-  double qb[4], fW[4], fE[4], fS[4], fN[4], nW[4], nE[4], nS[4], nN[4];
+  double fW[4], fE[4], fS[4], fN[4], nW[4], nE[4], nS[4], nN[4];
   int Iw = I - 1, Ie = I + 1, Js = J - 1, Jn = J + 1;
   if (G.periodic) {
     Iw = (Iw + G.nx) % G.nx; Ie = Ie % G.nx;
@@ -154,13 +156,9 @@ __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, L
     nS[k] = A.qbar[k * ne + Js * G.nx + I];
     nN[k] = A.qbar[k * ne + Jn * G.nx + I];
   }
-  if (!(qb[0] > 0.0)) {
-    atomicOr(A.err, 1);
-    return;
-  }
+  if (!(qb[0] > 0.0)) return false;
 
-  bool troubled = false;
-  double slope[2][4];
+  troubled = false;
 #pragma unroll
   for (int ax = 0; ax < 2; ++ax) {
     double Rm[4][4], Lm[4][4];
@@ -197,10 +195,39 @@ __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, L
     matvec(Rm, sc, slope[ax]);
   }
 
-  if (A.flags != nullptr) A.flags[e] = troubled ? 1 : 0;
+  return true;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, LimitArgs A) {
+  constexpr int N1 = P + 1, NSP = N1 * N1;
+  if (A.skip != nullptr && *A.skip != 0) return;  // the same for every block
+  __shared__ int wave_count[4];
+  const int ne = G.nx * G.ny;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t plane = (size_t)ne * NSP;
+  bool troubled = false;
+  double qb[4], slope[2][4];
+  if (e < ne) {
+    if (!limit_element<P>(G, W, A, e, qb, slope, troubled))
+      atomicOr(A.err, 1);
+    else if (A.flags != nullptr)
+      A.flags[e] = troubled ? 1 : 0;
+  }
+
+  // the block's troubled elements: one count per wave, summed by one thread;
+  // the running total has a slot per block, so no two blocks add to the
+  // same address (a thousand atomics on one address serialise at the L2)
+  const unsigned long long tw = __ballot(troubled);
+  if ((threadIdx.x & 63) == 0) wave_count[threadIdx.x >> 6] = __popcll(tw);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) n += wave_count[w];
+    if (A.count != nullptr && n != 0) atomicAdd(A.count, n);
+    if (A.total != nullptr) A.total[blockIdx.x] += (unsigned long long)n;
+  }
   if (!troubled) return;
-  if (A.count != nullptr) atomicAdd(A.count, 1);
-  if (A.total != nullptr) atomicAdd(A.total, 1ull);
   const double hx = 0.5 * G.dx, hy = 0.5 * G.dy;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -213,12 +240,13 @@ __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, L
   }
 }
 
+int limit_blocks(const Geometry& g) { return (g.nx * g.ny + 255) / 256; }
+
 template <int P>
 static hipError_t launch_limit_t(const Geometry& g, const Tables1D& T, const LimitArgs& a,
                                  hipStream_t s) {
   const WTab<P + 1> w = make_wtab<P + 1>(T);
-  const int ne = g.nx * g.ny;
-  const dim3 grid((ne + 255) / 256), block(256);
+  const dim3 grid(limit_blocks(g)), block(256);
   if (!a.means_ready) hipLaunchKernelGGL((means_kernel<P>), grid, block, 0, s, g, w, a);
   hipLaunchKernelGGL((limit_kernel<P>), grid, block, 0, s, g, w, a);
   return hipGetLastError();

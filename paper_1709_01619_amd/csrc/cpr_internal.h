@@ -89,8 +89,9 @@ struct LimitArgs {
   double* q;
   double* qbar;     // 4 * ny * nx scratch
   int* flags;       // nullable, ny * nx
-  int* count;       // nullable device counter (atomic add of troubled elements)
-  unsigned long long* total;  // nullable running total of troubled elements
+  int* count;       // nullable device counter of troubled elements (atomic add per block)
+  unsigned long long* total;  // nullable running total of troubled elements, one slot
+                              // per block of the limiter's grid (limit_blocks slots)
   double tvb_m;
   const int* skip;  // nullable
   int* err;
@@ -98,6 +99,8 @@ struct LimitArgs {
 };
 hipError_t launch_limit(int P, const Geometry& g, const Tables1D& T, const LimitArgs& a,
                         hipStream_t s);
+// blocks of the limiter's grid
+int limit_blocks(const Geometry& g);
 
 // Reductions. partials must hold reduce_partials_size() doubles.
 size_t reduce_partials_size(int P, const Geometry& g);
