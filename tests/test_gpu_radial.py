@@ -65,6 +65,29 @@ def test_radial_tube_three_steps_match_oracle(scheme, P, cfl):
     assert rel_err(host(qd), qo) <= 1e-11
 
 
+@pytest.mark.parametrize("scheme,P,cfl", CASES)
+def test_radial_tube_fifteen_steps_match_oracle_on_paper_mesh(scheme, P, cfl):
+    """Element by element on the paper's 200x200 mesh: the initial limiting
+    and 15 limited steps (the oracle's own CFL dt) against the oracle."""
+    g = _grid(scheme, P, 200)
+    x, y = g.coords()
+    q = inputs.radial_shock_tube(x, y)
+    say("radial tube 200 parity", scheme, P)
+
+    def lim(z):
+        return limiter.limit(z, g, M=10.0)
+
+    s = make_solver(g, limiter=True, tvb_m=10.0)
+    qo = lim(q)
+    qd = dev(q)
+    s.limit(qd)
+    for _ in range(15):
+        dt = cpr.cfl_dt(qo, g, cfl)
+        qo = cpr.rk3_step(qo, dt, g, limit=lim)
+        s.step(qd, dt, limit=True)
+    assert rel_err(host(qd), qo) <= 1e-11
+
+
 def _gpu_run(scheme, P, n, cfl):
     g = _grid(scheme, P, n)
     x, y = g.coords()

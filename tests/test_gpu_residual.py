@@ -190,6 +190,45 @@ def test_residual_transpose_bitwise(P, prec, bc):
     assert np.array_equal(rt, r[[0, 2, 1, 3]].transpose(0, 2, 1, 4, 3))
 
 
+@pytest.mark.parametrize("P,prec", [(1, "fp64"), (2, "fp64"), (3, "fp64"), (4, "fp64"),
+                                    (3, "fp32_bulk"), (4, "fp32_bulk")])
+@pytest.mark.parametrize("scheme", ["gl_lp", "gll_chain"])
+def test_residual_and_transpose_shift_invariant(P, prec, scheme):
+    """On a periodic mesh, shifting the state by (3, 5) elements moves every
+    element to another place in its 8x8 tile, turning interior faces into
+    tile-boundary faces and back: in float64 the residual and the transpose
+    of the shifted state must be the shifted results, bit for bit, whatever
+    the tile decomposition. FP32-bulk forms a tile-boundary face state in
+    the neighbour line's frame before moving it into its own, so there the
+    two agree within the float32 forward-error bounds of the FP32-bulk tests
+    (each side within its bound of the float64 result)."""
+    g = cpr.Grid(P=P, nx=40, ny=36, x0=0.0, x1=2.0, y0=0.0, y1=1.8, scheme=scheme)
+    q = inputs.random_state((36, 40, P + 1, P + 1), seed=700 + P)
+    v = np.random.default_rng(710 + P).standard_normal(g.shape)
+    say("shift invariance", P, prec, scheme)
+
+    def sh(a):
+        return np.ascontiguousarray(np.roll(a, (5, 3), axis=(1, 2)))
+
+    s = make_solver(g, precision=prec)
+    r = host(s.residual(dev(q))).astype(np.float64)
+    rs = host(s.residual(dev(sh(q)))).astype(np.float64)
+    o = host(s.residual_vjp(dev(q), dev(v)))
+    os_ = host(s.residual_vjp(dev(sh(q)), dev(sh(v))))
+    if prec == "fp64":
+        assert np.array_equal(rs, sh(r))
+        assert np.array_equal(os_, sh(o))
+        return
+    from tests.test_gpu_fp32_deviation import _bounds
+    if scheme == "gll_chain":
+        from tests.test_gpu_chain import _chain_vjp_fp32_scale as vjp_scale
+    else:
+        from tests.test_gpu_limiter_adjoint import _vjp_fp32_scale as vjp_scale
+    bound_r, _ = _bounds(q, g, cpr.residual(q, g))
+    assert np.max(np.abs(rs - sh(r))) <= 2 * bound_r
+    assert np.max(np.abs(os_ - sh(o))) <= 2 * 64 * 2.0 ** -24 * vjp_scale(q, v, g)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32_bulk"])
 @pytest.mark.parametrize("P", [2, 3, 4])
 @pytest.mark.parametrize("nx", [13, 14])
