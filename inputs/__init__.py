@@ -134,6 +134,20 @@ def radial_shock_tube(x, y, gamma=GAMMA, radius=0.4, inside=(1.0, 1.0),
     return conserved_from_primitive(rho, zero, zero, p, gamma)
 
 
+# The largest CFL the paper lists for each method on this problem (Table 4),
+# by degree and mesh (160k/640k unknowns per variable at P1 are 200^2/400^2
+# elements, 360k/1440k at P2 likewise). Keys: the scheme that reproduces each
+# method here (gl_lp: DG, gll_chain: CPR, gll_lp: NDG).
+RADIAL_TUBE_CFL = {
+    ("gl_lp", 1, 200): 0.22, ("gl_lp", 1, 400): 0.2,
+    ("gl_lp", 2, 200): 0.08, ("gl_lp", 2, 400): 0.08,
+    ("gll_chain", 1, 200): 0.2, ("gll_chain", 1, 400): 0.2,
+    ("gll_chain", 2, 200): 0.1, ("gll_chain", 2, 400): 0.1,
+    ("gll_lp", 1, 200): 0.2, ("gll_lp", 1, 400): 0.2,
+    ("gll_lp", 2, 200): 0.1, ("gll_lp", 2, 400): 0.1,
+}
+
+
 # ----------------------------------------------------------------------------
 # Entropy (density) wave: rho = 1 + a sin(2 pi (x+y)/L), u = v = 1, p = 1,
 # advected unchanged; a smooth periodic field with no vortex tail.
