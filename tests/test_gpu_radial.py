@@ -81,9 +81,12 @@ def test_radial_tube_fifteen_steps_match_oracle_on_paper_mesh(scheme, P):
     x, y = g.coords()
     q = inputs.radial_shock_tube(x, y)
     say("radial tube 200 parity", scheme, P)
+    flagged = [0]
 
     def lim(z):
-        return limiter.limit(z, g, M=10.0)
+        out, fl = limiter.limit(z, g, M=10.0, return_flags=True)
+        flagged[0] += int(fl.sum())
+        return out
 
     s = make_solver(g, limiter=True, tvb_m=10.0)
     qo = lim(q)
@@ -94,6 +97,9 @@ def test_radial_tube_fifteen_steps_match_oracle_on_paper_mesh(scheme, P):
         qo = cpr.rk3_step(qo, dt, g, limit=lim)
         s.step(qd, dt, limit=True)
     assert rel_err(host(qd), qo) <= 1e-11
+    # the running total over 46 passes, summed from the limiter's per-block
+    # slots (157 blocks of 256 elements, the last one partly empty)
+    assert s.troubled_total() == flagged[0] > 0
 
 
 def _gpu_run(scheme, P, n, cfl):

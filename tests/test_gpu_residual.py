@@ -190,6 +190,28 @@ def test_residual_transpose_bitwise(P, prec, bc):
     assert np.array_equal(rt, r[[0, 2, 1, 3]].transpose(0, 2, 1, 4, 3))
 
 
+@pytest.mark.parametrize("P,n", [(3, 256), (2, 333)])
+def test_max_wavespeed_large_mesh(P, n):
+    """The CFL wave speed on meshes whose points outnumber the reduction's
+    threads (each block takes a grid-strided share, writes its maximum, and
+    one block reduces the maxima): equal to the oracle's maximum to rounding,
+    and on a state whose largest speed sits at one known point, at the last
+    point of the mesh and at the first."""
+    from oracle import euler
+    g = cpr.Grid(P=P, nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0)
+    q = inputs.random_state((n, n, P + 1, P + 1), seed=950 + P)
+    say("max wavespeed large mesh", P, n)
+    s = make_solver(g)
+    lam = float(np.max(euler.max_wave_speed(q, g.gamma)))
+    assert abs(s.max_wavespeed(dev(q)) - lam) <= 1e-14 * lam
+    for idx in ((n - 1, n - 1, P, P), (0, 0, 0, 0)):
+        qq = q.copy()
+        qq[1][idx] = 40.0 * qq[0][idx]  # u = 40 at that point only
+        qq[3][idx] += 0.5 * qq[1][idx] ** 2 / qq[0][idx]
+        lam = float(np.max(euler.max_wave_speed(qq, g.gamma)))
+        assert abs(s.max_wavespeed(dev(qq)) - lam) <= 1e-14 * lam
+
+
 @pytest.mark.parametrize("P,prec", [(1, "fp64"), (2, "fp64"), (3, "fp64"), (4, "fp64"),
                                     (3, "fp32_bulk"), (4, "fp32_bulk")])
 @pytest.mark.parametrize("scheme", ["gl_lp", "gll_chain"])
