@@ -27,7 +27,9 @@
 //  A  the tile (4 variables x 64 elements x (P+1)^2 float64) is copied into
 //     LDS with coalesced loads; lanes 0..32(P+1)-1 also load the line of the
 //     neighbouring element across the tile boundary that they own. All of
-//     a wave's loads are issued before any is used: one memory round trip;
+//     a wave's copy loads are issued before any is used: one memory round
+//     trip. The scattered neighbour-line loads go out with them, or in
+//     float64 from P = 2 just after the copies are in LDS;
 //  B  those lanes finish the Rusanov flux on the tile-boundary faces; every
 //     lane reads its column out of LDS;
 //  C  column sweep: interior face states travel between lanes by wave
@@ -142,43 +144,54 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
         }
       }
     }
+    // the outside neighbour lines of the tile-boundary lanes are scattered
+    // loads. In float64 from P = 2 they are issued once the tile's coalesced
+    // copies are written to LDS: a second round trip for those lanes, but the
+    // copies no longer queue behind them and the copy registers are free
+    // (P = 4 1024^2: 657 -> 605 us per launch; P = 2: 128 -> 95 VGPRs, five
+    // waves per SIMD, the limited 512^2 step 233 -> 229 us). In float32 and
+    // at P = 1 they go out with the copies (the later order measured 1-2 %
+    // slower there).
+    constexpr bool HALO_LATE = sizeof(R) == 8 && N1 >= 3;
     double hraw[4][N1];
-    if (halo) {
-      hs = tid / (kTile * N1);
-      const int r2 = tid - hs * (kTile * N1);
-      hp = r2 / N1;
-      hm = r2 - hp * N1;
-      int Io, Jo;
-      if (hs < 2) {
-        hact = hp < nay;
-        Jo = J0 + hp;
-        Io = (hs == 0) ? I0 - 1 : I0 + nax;
-      } else {
-        hact = hp < nax;
-        Io = I0 + hp;
-        Jo = (hs == 2) ? J0 - 1 : J0 + nay;
-      }
-      hout = true;
-      if (Io < 0 || Io >= G.nx) {
-        if (G.periodic) Io = (Io + G.nx) % G.nx; else hout = false;
-      }
-      if (Jo < 0 || Jo >= G.ny) {
-        if (G.periodic) Jo = (Jo + G.ny) % G.ny; else hout = false;
-      }
-      if (hact && hout) {
-        const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
-        if (LOB) {
-          // the neighbour's end point on the face that touches this tile
-          const int nf = (hs == 0 || hs == 2) ? N1 - 1 : 0;
-#pragma unroll
-          for (int k = 0; k < 4; ++k)
-            hraw[k][0] = base[k * plane + (hs < 2 ? hm * N1 + nf : nf * N1 + hm)];
+    if constexpr (!HALO_LATE) {
+      if (halo) {
+        hs = tid / (kTile * N1);
+        const int r2 = tid - hs * (kTile * N1);
+        hp = r2 / N1;
+        hm = r2 - hp * N1;
+        int Io, Jo;
+        if (hs < 2) {
+          hact = hp < nay;
+          Jo = J0 + hp;
+          Io = (hs == 0) ? I0 - 1 : I0 + nax;
         } else {
+          hact = hp < nax;
+          Io = I0 + hp;
+          Jo = (hs == 2) ? J0 - 1 : J0 + nay;
+        }
+        hout = true;
+        if (Io < 0 || Io >= G.nx) {
+          if (G.periodic) Io = (Io + G.nx) % G.nx; else hout = false;
+        }
+        if (Jo < 0 || Jo >= G.ny) {
+          if (G.periodic) Jo = (Jo + G.ny) % G.ny; else hout = false;
+        }
+        if (hact && hout) {
+          const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
+          if (LOB) {
+            // the neighbour's end point on the face that touches this tile
+            const int nf = (hs == 0 || hs == 2) ? N1 - 1 : 0;
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
+            for (int k = 0; k < 4; ++k)
+              hraw[k][0] = base[k * plane + (hs < 2 ? hm * N1 + nf : nf * N1 + hm)];
+          } else {
 #pragma unroll
-            for (int n = 0; n < N1; ++n)
-              hraw[k][n] = base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+              for (int n = 0; n < N1; ++n)
+                hraw[k][n] = base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+          }
         }
       }
     }
@@ -202,6 +215,48 @@ __global__ __launch_bounds__((64 * (P + 1) * TilesPerGroup<P + 1, R>::value)) vo
         for (int it = 0; it < TC::NIT; ++it) {
           const int f = it * 64 + lane;
           if (ok && f < seg_len) dst[tc.loff[it]] = v[u][it];
+        }
+      }
+    }
+    if constexpr (HALO_LATE) {
+      // the same task and loads as above, once the copies are in LDS
+      if (halo) {
+        hs = tid / (kTile * N1);
+        const int r2 = tid - hs * (kTile * N1);
+        hp = r2 / N1;
+        hm = r2 - hp * N1;
+        int Io, Jo;
+        if (hs < 2) {
+          hact = hp < nay;
+          Jo = J0 + hp;
+          Io = (hs == 0) ? I0 - 1 : I0 + nax;
+        } else {
+          hact = hp < nax;
+          Io = I0 + hp;
+          Jo = (hs == 2) ? J0 - 1 : J0 + nay;
+        }
+        hout = true;
+        if (Io < 0 || Io >= G.nx) {
+          if (G.periodic) Io = (Io + G.nx) % G.nx; else hout = false;
+        }
+        if (Jo < 0 || Jo >= G.ny) {
+          if (G.periodic) Jo = (Jo + G.ny) % G.ny; else hout = false;
+        }
+        if (hact && hout) {
+          const double* base = A.q_src + ((size_t)Jo * G.nx + Io) * NSP;
+          if (LOB) {
+            // the neighbour's end point on the face that touches this tile
+            const int nf = (hs == 0 || hs == 2) ? N1 - 1 : 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              hraw[k][0] = base[k * plane + (hs < 2 ? hm * N1 + nf : nf * N1 + hm)];
+          } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+              for (int n = 0; n < N1; ++n)
+                hraw[k][n] = base[k * plane + (hs < 2 ? hm * N1 + n : n * N1 + hm)];
+          }
         }
       }
     }
