@@ -379,7 +379,9 @@ cpr_status cpr_residual_vjp(cpr_ctx* ctx, const double* q, const double* v, doub
 
 namespace {
 
-cpr_status adjoint_checks(cpr_ctx* ctx, const char* who) {
+// static: inside the extern "C" block the unnamed namespace alone leaves
+// these helpers among the library's exported symbols
+static cpr_status adjoint_checks(cpr_ctx* ctx, const char* who) {
   if (ctx->cfg.limiter != CPR_LIM_NONE) {
     set_err(ctx, "%s: the limiter is not differentiated", who);
     return CPR_EUNSUPPORTED;
@@ -388,8 +390,9 @@ cpr_status adjoint_checks(cpr_ctx* ctx, const char* who) {
 }
 
 // The three transposes of one SSP-RK3 step, given its stage states.
-cpr_status adjoint_sweep(cpr_ctx* ctx, const double* q_n, const double* q1, const double* q2,
-                         double dt, const double* lam_np1, double* lam_n) {
+static cpr_status adjoint_sweep(cpr_ctx* ctx, const double* q_n, const double* q1,
+                                const double* q2, double dt, const double* lam_np1,
+                                double* lam_n) {
   cpr_status st;
   // lam2 = 2/3 (lam3 + dt J(q2)^T lam3)
   if ((st = vjp(ctx, q2, lam_np1, nullptr, nullptr, ctx->lam2, 2.0 / 3.0, 2.0 / 3.0 * dt, 0.0, 0.0)) != CPR_OK) return st;

@@ -57,37 +57,66 @@ __global__ __launch_bounds__(256) void means_kernel(Geometry G, WTab<P + 1> W, L
 }
 
 // Right (R) and left (L = R^-1) eigenvectors of the flux Jacobian in
-// direction AX at state qb, rows/columns in (rho, rho u, rho v, e) order.
-template <int AX>
-__device__ void char_mats(const double qb[4], double gamma, double Rm[4][4], double Lm[4][4]) {
+// direction n at state qb, in (rho, m_n, m_t, e) order, where m_n and m_t
+// are the momenta normal and tangential to n. The x direction takes
+// (m_n, m_t) = (rho u, rho v), the y direction (rho v, rho u). The rows are
+// formed one at a time from these scalars where they are used, so that no
+// 4x4 matrix is held in registers.
+struct CharState {
+  double u, v, ke, c, H, b1, b2;
+};
+
+__device__ __forceinline__ CharState char_state(const double qb[4], double gamma) {
+  CharState s;
   const double rho = qb[0];
-  const double u = qb[1] / rho, v = qb[2] / rho;
-  const double ke = 0.5 * sym_dot2(u, u, v, v);
-  const double p = (gamma - 1.0) * (qb[3] - rho * ke);
-  const double c = sqrt(gamma * p / rho);
-  const double H = (qb[3] + p) / rho;
-  const double b1 = (gamma - 1.0) / (c * c);
-  const double b2 = ke * b1;
-  const double un = AX == 0 ? u : v;
-  const double ut = AX == 0 ? v : u;
-  constexpr int in = AX == 0 ? 1 : 2;  // normal momentum index
-  constexpr int it = AX == 0 ? 2 : 1;  // tangential momentum index
-  const double rn[4][4] = {{1.0, 1.0, 0.0, 1.0},
-                           {un - c, un, 0.0, un + c},
-                           {ut, ut, 1.0, ut},
-                           {H - un * c, ke, ut, H + un * c}};
-  const double ln[4][4] = {{0.5 * (b2 + un / c), -0.5 * (b1 * un + 1.0 / c), -0.5 * b1 * ut, 0.5 * b1},
-                           {1.0 - b2, b1 * un, b1 * ut, -b1},
-                           {-ut, 0.0, 1.0, 0.0},
-                           {0.5 * (b2 - un / c), -0.5 * (b1 * un - 1.0 / c), -0.5 * b1 * ut, 0.5 * b1}};
-  const int map[4] = {0, in, it, 3};  // (rho, m_n, m_t, e) -> variable index
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      Rm[map[a]][b] = rn[a][b];
-      Lm[a][map[b]] = ln[a][b];
-    }
+  s.u = qb[1] / rho;
+  s.v = qb[2] / rho;
+  s.ke = 0.5 * sym_dot2(s.u, s.u, s.v, s.v);
+  const double p = (gamma - 1.0) * (qb[3] - rho * s.ke);
+  s.c = sqrt(gamma * p / rho);
+  s.H = (qb[3] + p) / rho;
+  s.b1 = (gamma - 1.0) / (s.c * s.c);
+  s.b2 = s.ke * s.b1;
+  return s;
+}
+
+// Row a of L in direction AX, as coefficients of (rho, m_n, m_t, e).
+template <int AX>
+__device__ __forceinline__ void left_row(const CharState& s, int a, double r[4]) {
+  const double un = AX == 0 ? s.u : s.v;
+  const double ut = AX == 0 ? s.v : s.u;
+  const double b1 = s.b1, b2 = s.b2, c = s.c;
+  if (a == 0) {
+    r[0] = 0.5 * (b2 + un / c); r[1] = -0.5 * (b1 * un + 1.0 / c);
+    r[2] = -0.5 * b1 * ut;      r[3] = 0.5 * b1;
+  }
+  if (a == 1) { r[0] = 1.0 - b2; r[1] = b1 * un; r[2] = b1 * ut; r[3] = -b1; }
+  if (a == 2) { r[0] = -ut; r[1] = 0.0; r[2] = 1.0; r[3] = 0.0; }
+  if (a == 3) {
+    r[0] = 0.5 * (b2 - un / c); r[1] = -0.5 * (b1 * un - 1.0 / c);
+    r[2] = -0.5 * b1 * ut;      r[3] = 0.5 * b1;
+  }
+}
+
+// Row a of R in direction AX (component a of (rho, m_n, m_t, e)), as
+// coefficients of the four characteristic variables.
+template <int AX>
+__device__ __forceinline__ void right_row(const CharState& s, int a, double r[4]) {
+  const double un = AX == 0 ? s.u : s.v;
+  const double ut = AX == 0 ? s.v : s.u;
+  const double c = s.c;
+  if (a == 0) { r[0] = 1.0; r[1] = 1.0; r[2] = 0.0; r[3] = 1.0; }
+  if (a == 1) { r[0] = un - c; r[1] = un; r[2] = 0.0; r[3] = un + c; }
+  if (a == 2) { r[0] = ut; r[1] = ut; r[2] = 1.0; r[3] = ut; }
+  if (a == 3) { r[0] = s.H - un * c; r[1] = s.ke; r[2] = ut; r[3] = s.H + un * c; }
+}
+
+// r . (x0, xn, xt, x3): the normal and tangential momentum terms are summed
+// as a pair, so that the x and y directions of transposed data round
+// identically.
+__device__ __forceinline__ double row_dot(const double r[4], double x0, double xn, double xt,
+                                          double x3) {
+  return fma(r[0], x0, r[3] * x3) + sym_dot2(r[1], xn, r[2], xt);
 }
 
 __device__ __forceinline__ double minmod3(double a, double b, double c) {
@@ -97,12 +126,59 @@ __device__ __forceinline__ double minmod3(double a, double b, double c) {
   return pos ? m : (neg ? -m : 0.0);
 }
 
-// y = M x, summing the two momentum columns as a pair so that the x and y
-// directions of transposed data round identically.
-__device__ __forceinline__ void matvec(const double M[4][4], const double x[4], double y[4]) {
+// One direction of the TVB test: lo and hi are the element's face means on
+// the low and high side, nlo and nhi the neighbour means there. Sets
+// troubled if the modified minmod changes a face deviation, and writes the
+// limited slope (component order rho, rho u, rho v, e).
+template <int AX>
+__device__ __forceinline__ void limit_direction(const CharState& s, const double qb[4],
+                                                const double lo[4], const double hi[4],
+                                                const double nlo[4], const double nhi[4],
+                                                double h, double tvb_m, bool& troubled,
+                                                double slope[4]) {
+  constexpr int in = AX == 0 ? 1 : 2, it = AX == 0 ? 2 : 1;
+  double t0[4], t1[4], t2[4], t3[4], t4[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-    y[a] = fma(M[a][0], x[0], M[a][3] * x[3]) + sym_dot2(M[a][1], x[1], M[a][2], x[2]);
+  for (int k = 0; k < 4; ++k) {
+    t0[k] = hi[k] - qb[k];
+    t1[k] = qb[k] - lo[k];
+    t2[k] = nhi[k] - qb[k];
+    t3[k] = qb[k] - nlo[k];
+    t4[k] = hi[k] - lo[k];
+  }
+  const double bound = tvb_m * h * h;
+  double sc[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double r[4];
+    left_row<AX>(s, a, r);
+    const double up = row_dot(r, t0[0], t0[in], t0[it], t0[3]);
+    const double um = row_dot(r, t1[0], t1[in], t1[it], t1[3]);
+    const double dp = row_dot(r, t2[0], t2[in], t2[it], t2[3]);
+    const double dm = row_dot(r, t3[0], t3[in], t3[it], t3[3]);
+    const double dd = row_dot(r, t4[0], t4[in], t4[it], t4[3]);
+    // the TVB-modified minmod leaves a deviation within bound unchanged and
+    // otherwise replaces it by minmod(deviation, dp, dm); the element is
+    // troubled when a deviation changes. Both minmods are formed and the
+    // test is taken without branches.
+    const double mp = minmod3(up, dp, dm);
+    const double mm = minmod3(um, dp, dm);
+    troubled = troubled | (!(fabs(up) <= bound) & (mp != up)) |
+               (!(fabs(um) <= bound) & (mm != um));
+    // minmod of the three differences over h, with one division: for h > 0
+    // the rounded quotient is monotone in its numerator and keeps its sign,
+    // so minmod(x/h, y/h, z/h) and minmod(x, y, z)/h are the same value (a
+    // zero result can differ in sign only where a difference underflows
+    // to zero on division, which needs h > 1)
+    sc[a] = minmod3(dd, dp, dm) / h;
+  }
+  const int comp[4] = {0, in, it, 3};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    double r[4];
+    right_row<AX>(s, a, r);
+    slope[comp[a]] = row_dot(r, sc[0], sc[1], sc[2], sc[3]);
+  }
 }
 
 // ---------------------------------------------------- detect and limit --
@@ -118,7 +194,7 @@ __device__ __forceinline__ bool limit_element(const Geometry& G, const WTab<P + 
   const int ne = G.nx * G.ny;
   const size_t plane = (size_t)ne * NSP;
 
-  double fW[4], fE[4], fS[4], fN[4], nW[4], nE[4], nS[4], nN[4];
+  double fW[4], fE[4], fS[4], fN[4];
   int Iw = I - 1, Ie = I + 1, Js = J - 1, Jn = J + 1;
   if (G.periodic) {
     Iw = (Iw + G.nx) % G.nx; Ie = Ie % G.nx;
@@ -151,50 +227,29 @@ __device__ __forceinline__ bool limit_element(const Geometry& G, const WTab<P + 
     fS[k] = 0.5 * s_;
     fN[k] = 0.5 * n_;
     qb[k] = A.qbar[k * ne + e];
-    nW[k] = A.qbar[k * ne + J * G.nx + Iw];
-    nE[k] = A.qbar[k * ne + J * G.nx + Ie];
-    nS[k] = A.qbar[k * ne + Js * G.nx + I];
-    nN[k] = A.qbar[k * ne + Jn * G.nx + I];
   }
   if (!(qb[0] > 0.0)) return false;
 
+  const CharState cs = char_state(qb, G.gamma);
   troubled = false;
-#pragma unroll
-  for (int ax = 0; ax < 2; ++ax) {
-    double Rm[4][4], Lm[4][4];
-    if (ax == 0) char_mats<0>(qb, G.gamma, Rm, Lm); else char_mats<1>(qb, G.gamma, Rm, Lm);
-    const double* lo = ax == 0 ? fW : fS;
-    const double* hi = ax == 0 ? fE : fN;
-    const double* nlo = ax == 0 ? nW : nS;
-    const double* nhi = ax == 0 ? nE : nN;
-    const double h = ax == 0 ? G.dx : G.dy;
-    double t0[4], t1[4], t2[4], t3[4], t4[4];
+  {
+    double nW[4], nE[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      t0[k] = hi[k] - qb[k];
-      t1[k] = qb[k] - lo[k];
-      t2[k] = nhi[k] - qb[k];
-      t3[k] = qb[k] - nlo[k];
-      t4[k] = hi[k] - lo[k];
+      nW[k] = A.qbar[k * ne + J * G.nx + Iw];
+      nE[k] = A.qbar[k * ne + J * G.nx + Ie];
     }
-    double up[4], um[4], dp[4], dm[4], dd[4];
-    matvec(Lm, t0, up);
-    matvec(Lm, t1, um);
-    matvec(Lm, t2, dp);
-    matvec(Lm, t3, dm);
-    matvec(Lm, t4, dd);
-    const double bound = A.tvb_m * h * h;
-    double sc[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const double mp = fabs(up[a]) <= bound ? up[a] : minmod3(up[a], dp[a], dm[a]);
-      const double mm = fabs(um[a]) <= bound ? um[a] : minmod3(um[a], dp[a], dm[a]);
-      troubled = troubled || (mp != up[a]) || (mm != um[a]);
-      sc[a] = minmod3(dd[a] / h, dp[a] / h, dm[a] / h);
-    }
-    matvec(Rm, sc, slope[ax]);
+    limit_direction<0>(cs, qb, fW, fE, nW, nE, G.dx, A.tvb_m, troubled, slope[0]);
   }
-
+  {
+    double nS[4], nN[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      nS[k] = A.qbar[k * ne + Js * G.nx + I];
+      nN[k] = A.qbar[k * ne + Jn * G.nx + I];
+    }
+    limit_direction<1>(cs, qb, fS, fN, nS, nN, G.dy, A.tvb_m, troubled, slope[1]);
+  }
   return true;
 }
 
