@@ -326,27 +326,37 @@ def limited_riemann():
     q = torch.from_numpy(inputs.riemann_quadrants(x.cpu().numpy(), y.cpu().numpy())).cuda()
     s.set_time(0.0)
     s.limit(q)
-    g = s.capture_steps(q, 0.0, 100, limit=True)   # recording runs nothing
+    # recording runs nothing; a replay of n steps is taken only where n steps
+    # at 1.25 times the last dt stay short of t_end, so that no recorded step
+    # reaches t_end (after it, steps do nothing and could not be counted)
+    sizes = (500, 50, 5)
+    graphs = {n: s.capture_steps(q, 0.0, n, limit=True) for n in sizes}
     s.troubled_total(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    steps, t = 0, 0.0
-    while t < 0.29 and steps < 20000:      # graph replays of 100 steps well before t_end
-        g.replay()
-        steps += 100
-        t, _ = s.get_time()
-    while t < 0.3 * (1 - 1e-14) and steps < 20000:   # then one at a time, to count exactly
-        s.step(q, 0.0, limit=True)
-        steps += 1
-        t, _ = s.get_time()
+    steps, t, dt = 0, 0.0, 0.0
+    t_end = 0.3
+    while t < t_end * (1 - 1e-14) and steps < 20000:
+        k = next((m for m in sizes if dt > 0.0 and t + 1.25 * m * dt < t_end), 0)
+        if k:
+            graphs[k].replay()
+            steps += k
+        else:
+            s.step(q, 0.0, limit=True)
+            steps += 1
+        t, dt = s.get_time()
+        if k and t >= t_end * (1 - 1e-14):
+            raise RuntimeError("a replayed graph reached t_end: its step count is not exact")
     el = time.perf_counter() - t0
     ndone = steps
     total = s.troubled_total()
     qt = q[[0, 2, 1, 3]].permute(0, 2, 1, 4, 3)
     sym = float((q - qt).abs().max().item())
     return {"workload": "P=2 Riemann 512x512 transmissive, TVB M=10 after every stage, "
-                        "CFL 0.1 device dt, to t=0.3 (steps replayed from a 100-step HIP "
-                        "graph, the last ones launched one by one)",
+                        "CFL 0.1 device dt, to t=0.3 (steps replayed from HIP graphs of 500, "
+                        "50 or 5 steps, each taken only where it stays short of t=0.3 at "
+                        "1.25 times the last dt; the last ones launched one by one; the time "
+                        "is read after each)",
             "steps": ndone, "t_final": t, "s_per_step": el / ndone,
             "troubled_element_passes": total,
             "troubled_fraction_mean": total / (3.0 * ndone * n * n),

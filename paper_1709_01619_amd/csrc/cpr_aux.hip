@@ -378,26 +378,39 @@ hipError_t launch_max_wavespeed(int P, const Geometry& g, const double* q, doubl
   return hipGetLastError();
 }
 
-// the largest of part[0 .. n) (all >= 0), in one block of kRedBlock threads
+// the largest of part[0 .. n) (all >= 0), in one block of kRedBlock threads:
+// each thread's loads go out together (one memory round trip for n up to
+// 4 kRedBlock, where a plain strided loop waits on each load in turn), then
+// the maximum is taken within each wave by shuffles and over the waves in
+// LDS; the maximum is exact in any order
 __device__ __forceinline__ double block_max_parts(const double* part, int n, double* red) {
+  constexpr int U = 4;
   double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += kRedBlock) m = fmax(m, part[i]);
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = kRedBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
+  for (int i0 = threadIdx.x; i0 < n; i0 += U * kRedBlock) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * kRedBlock;
+      v[u] = i < n ? part[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) m = fmax(m, v[u]);
   }
-  return red[0];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < kRedBlock / 64; ++w) r = fmax(r, red[w]);
+  return r;
 }
 
-__global__ __launch_bounds__(kRedBlock) void cfl_dt_kernel(const double* part, int nparts, double cfl,
-                                                           double h, double t_end, double* t,
-                                                           double* dt, int* skip) {
-  __shared__ double red[kRedBlock];
-  const double lam = block_max_parts(part, nparts, red);
-  if (threadIdx.x != 0) return;
-  const double tn = *t;
+// The step's dt from the largest wave speed lam and the time tn, by thread
+// 0: dt = min(cfl h / lam, t_end - tn) and t += dt, or skip once t_end is
+// reached (t_end > 0).
+__device__ __forceinline__ void cfl_dt_store(double lam, double tn, double cfl, double h,
+                                             double t_end, double* t, double* dt, int* skip) {
   if (t_end > 0.0 && t_end - tn <= 1e-14 * t_end) {
     *skip = 1;
     *dt = 0.0;
@@ -410,6 +423,17 @@ __global__ __launch_bounds__(kRedBlock) void cfl_dt_kernel(const double* part, i
   *skip = 0;
 }
 
+__global__ __launch_bounds__(kRedBlock) void cfl_dt_kernel(const double* part, int nparts, double cfl,
+                                                           double h, double t_end, double* t,
+                                                           double* dt, int* skip) {
+  __shared__ double red[kRedBlock / 64];
+  // read before the reduction's barrier, so that its latency overlaps the
+  // partials' and no thread reads t after thread 0 writes it
+  const double tn = *t;
+  const double lam = block_max_parts(part, nparts, red);
+  if (threadIdx.x == 0) cfl_dt_store(lam, tn, cfl, h, t_end, t, dt, skip);
+}
+
 hipError_t launch_cfl_dt(const double* part, int nparts, double cfl, double h, double t_end,
                          double* t, double* dt, int* skip, hipStream_t s) {
   hipLaunchKernelGGL(cfl_dt_kernel, dim3(1), dim3(kRedBlock), 0, s, part, nparts, cfl, h, t_end, t,
@@ -419,7 +443,7 @@ hipError_t launch_cfl_dt(const double* part, int nparts, double cfl, double h, d
 
 __global__ __launch_bounds__(kRedBlock) void max_parts_kernel(const double* part, int nparts,
                                                               double* out) {
-  __shared__ double red[kRedBlock];
+  __shared__ double red[kRedBlock / 64];
   const double m = block_max_parts(part, nparts, red);
   if (threadIdx.x == 0) *out = m;
 }
