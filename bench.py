@@ -327,7 +327,7 @@ def limited_riemann():
     s.set_time(0.0)
     s.limit(q)
     # recording runs nothing; a replay of n steps is taken only where n steps
-    # at 1.25 times the last dt stay short of t_end, so that no recorded step
+    # at twice the last dt stay short of t_end, so that no recorded step
     # reaches t_end (after it, steps do nothing and could not be counted)
     sizes = (500, 50, 5)
     graphs = {n: s.capture_steps(q, 0.0, n, limit=True) for n in sizes}
@@ -336,8 +336,9 @@ def limited_riemann():
     t0 = time.perf_counter()
     steps, t, dt = 0, 0.0, 0.0
     t_end = 0.3
+    exact = True
     while t < t_end * (1 - 1e-14) and steps < 20000:
-        k = next((m for m in sizes if dt > 0.0 and t + 1.25 * m * dt < t_end), 0)
+        k = next((m for m in sizes if dt > 0.0 and t + 2.0 * m * dt < t_end), 0)
         if k:
             graphs[k].replay()
             steps += k
@@ -346,7 +347,7 @@ def limited_riemann():
             steps += 1
         t, dt = s.get_time()
         if k and t >= t_end * (1 - 1e-14):
-            raise RuntimeError("a replayed graph reached t_end: its step count is not exact")
+            exact = False   # some of that replay's steps may have done nothing
     el = time.perf_counter() - t0
     ndone = steps
     total = s.troubled_total()
@@ -355,9 +356,9 @@ def limited_riemann():
     return {"workload": "P=2 Riemann 512x512 transmissive, TVB M=10 after every stage, "
                         "CFL 0.1 device dt, to t=0.3 (steps replayed from HIP graphs of 500, "
                         "50 or 5 steps, each taken only where it stays short of t=0.3 at "
-                        "1.25 times the last dt; the last ones launched one by one; the time "
+                        "twice the last dt; the last ones launched one by one; the time "
                         "is read after each)",
-            "steps": ndone, "t_final": t, "s_per_step": el / ndone,
+            "steps": ndone, "steps_exact": exact, "t_final": t, "s_per_step": el / ndone,
             "troubled_element_passes": total,
             "troubled_fraction_mean": total / (3.0 * ndone * n * n),
             "troubled_note": "troubled elements summed over all limiter passes (3 per step) / "
