@@ -2,11 +2,11 @@
 //
 // Limiter (Section 2.6 of arXiv:1709.01619, eq. limu, in the TVB
 // characteristic form of Cockburn and Shu that the paper cites): a means
-// pass writes every element's average; a second pass, one lane per element,
-// forms the face means of the extrapolated state, tests the face deviations
-// against the neighbour differences on characteristic variables with the
-// TVB minmod, and rewrites troubled elements as qbar + (x-x_I) s_x +
-// (y-y_J) s_y with characteristic minmod slopes.
+// pass writes every element's average; a second pass, two lanes per element
+// (one per direction), forms the face means of the extrapolated state, tests
+// the face deviations against the neighbour differences on characteristic
+// variables with the TVB minmod, and rewrites troubled elements as
+// qbar + (x-x_I) s_x + (y-y_J) s_y with characteristic minmod slopes.
 #include "cpr_device.h"
 
 namespace cpr {
@@ -80,11 +80,10 @@ __device__ __forceinline__ CharState char_state(const double qb[4], double gamma
   return s;
 }
 
-// Row a of L in direction AX, as coefficients of (rho, m_n, m_t, e).
-template <int AX>
-__device__ __forceinline__ void left_row(const CharState& s, int a, double r[4]) {
-  const double un = AX == 0 ? s.u : s.v;
-  const double ut = AX == 0 ? s.v : s.u;
+// Row a of L, as coefficients of (rho, m_n, m_t, e), for the velocity
+// components un normal and ut tangential to the direction.
+__device__ __forceinline__ void left_row(const CharState& s, double un, double ut, int a,
+                                         double r[4]) {
   const double b1 = s.b1, b2 = s.b2, c = s.c;
   if (a == 0) {
     r[0] = 0.5 * (b2 + un / c); r[1] = -0.5 * (b1 * un + 1.0 / c);
@@ -98,12 +97,10 @@ __device__ __forceinline__ void left_row(const CharState& s, int a, double r[4])
   }
 }
 
-// Row a of R in direction AX (component a of (rho, m_n, m_t, e)), as
-// coefficients of the four characteristic variables.
-template <int AX>
-__device__ __forceinline__ void right_row(const CharState& s, int a, double r[4]) {
-  const double un = AX == 0 ? s.u : s.v;
-  const double ut = AX == 0 ? s.v : s.u;
+// Row a of R (component a of (rho, m_n, m_t, e)), as coefficients of the
+// four characteristic variables.
+__device__ __forceinline__ void right_row(const CharState& s, double un, double ut, int a,
+                                          double r[4]) {
   const double c = s.c;
   if (a == 0) { r[0] = 1.0; r[1] = 1.0; r[2] = 0.0; r[3] = 1.0; }
   if (a == 1) { r[0] = un - c; r[1] = un; r[2] = 0.0; r[3] = un + c; }
@@ -126,37 +123,90 @@ __device__ __forceinline__ double minmod3(double a, double b, double c) {
   return pos ? m : (neg ? -m : 0.0);
 }
 
-// One direction of the TVB test: lo and hi are the element's face means on
-// the low and high side, nlo and nhi the neighbour means there. Sets
-// troubled if the modified minmod changes a face deviation, and writes the
-// limited slope (component order rho, rho u, rho v, e).
-template <int AX>
-__device__ __forceinline__ void limit_direction(const CharState& s, const double qb[4],
-                                                const double lo[4], const double hi[4],
-                                                const double nlo[4], const double nhi[4],
-                                                double h, double tvb_m, bool& troubled,
-                                                double slope[4]) {
-  constexpr int in = AX == 0 ? 1 : 2, it = AX == 0 ? 2 : 1;
+// ---------------------------------------------------- detect and limit --
+// Each element has two adjacent lanes: the even one takes the x direction
+// (west and east faces, extrapolated along rows), the odd one the y direction
+// (south and north faces, along columns). A lane picks its direction by
+// selects, not branches, so that both lanes of a pair run the same
+// instructions, and it forms every quantity by the same operations as the
+// direction alone would. limit_lane gives the element's mean qb, this
+// direction's limited slope sl (components rho, rho u, rho v, e; d/dx on the
+// x lane, d/dy on the y lane) and whether its TVB test finds the element
+// troubled; false when the mean density is not positive.
+template <int P>
+__device__ __forceinline__ bool limit_lane(const Geometry& G, const WTab<P + 1>& W,
+                                           const LimitArgs& A, int e, bool y, double qb[4],
+                                           double sl[4], bool& troubled) {
+  constexpr int N1 = P + 1, NSP = N1 * N1;
+  const int I = e % G.nx, J = e / G.nx;
+  const int ne = G.nx * G.ny;
+  const size_t plane = (size_t)ne * NSP;
+  // face means: each row (x) or column (y) extrapolated to its two ends,
+  // weighted along the face and halved (faces have length 2 in reference
+  // coordinates)
+  double lo[4], hi[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v[NSP];
+#pragma unroll
+    for (int p = 0; p < NSP; ++p) v[p] = A.q[k * plane + (size_t)e * NSP + p];
+    double l_ = 0.0, h_ = 0.0;
+#pragma unroll
+    for (int j = 0; j < N1; ++j) {
+      double rl = 0.0, rh = 0.0;
+#pragma unroll
+      for (int i = 0; i < N1; ++i) {
+        const double x = y ? v[i * N1 + j] : v[j * N1 + i];
+        rl = fma(W.em[i], x, rl);
+        rh = fma(W.ep[i], x, rh);
+      }
+      l_ = fma(W.w[j], rl, l_);
+      h_ = fma(W.w[j], rh, h_);
+    }
+    lo[k] = 0.5 * l_;
+    hi[k] = 0.5 * h_;
+    qb[k] = A.qbar[k * ne + e];
+  }
+  troubled = false;
+  if (!(qb[0] > 0.0)) return false;
+
+  // neighbour elements on the low and high side (the element itself past a
+  // transmissive boundary)
+  int nl, nh;
+  if (G.periodic) {
+    nl = y ? ((J - 1 + G.ny) % G.ny) * G.nx + I : J * G.nx + (I - 1 + G.nx) % G.nx;
+    nh = y ? ((J + 1) % G.ny) * G.nx + I : J * G.nx + (I + 1) % G.nx;
+  } else {
+    nl = y ? max(J - 1, 0) * G.nx + I : J * G.nx + max(I - 1, 0);
+    nh = y ? min(J + 1, G.ny - 1) * G.nx + I : J * G.nx + min(I + 1, G.nx - 1);
+  }
   double t0[4], t1[4], t2[4], t3[4], t4[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
+    const double nlo = A.qbar[k * ne + nl], nhi = A.qbar[k * ne + nh];
     t0[k] = hi[k] - qb[k];
     t1[k] = qb[k] - lo[k];
-    t2[k] = nhi[k] - qb[k];
-    t3[k] = qb[k] - nlo[k];
+    t2[k] = nhi - qb[k];
+    t3[k] = qb[k] - nlo;
     t4[k] = hi[k] - lo[k];
   }
-  const double bound = tvb_m * h * h;
+  const CharState s = char_state(qb, G.gamma);
+  const double un = y ? s.v : s.u, ut = y ? s.u : s.v;
+  const double h = y ? G.dy : G.dx;
+  const double bound = A.tvb_m * h * h;
+  // the normal and tangential momentum components of a difference
+  const auto mn = [&](const double* t) { return y ? t[2] : t[1]; };
+  const auto mt = [&](const double* t) { return y ? t[1] : t[2]; };
   double sc[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     double r[4];
-    left_row<AX>(s, a, r);
-    const double up = row_dot(r, t0[0], t0[in], t0[it], t0[3]);
-    const double um = row_dot(r, t1[0], t1[in], t1[it], t1[3]);
-    const double dp = row_dot(r, t2[0], t2[in], t2[it], t2[3]);
-    const double dm = row_dot(r, t3[0], t3[in], t3[it], t3[3]);
-    const double dd = row_dot(r, t4[0], t4[in], t4[it], t4[3]);
+    left_row(s, un, ut, a, r);
+    const double up = row_dot(r, t0[0], mn(t0), mt(t0), t0[3]);
+    const double um = row_dot(r, t1[0], mn(t1), mt(t1), t1[3]);
+    const double dp = row_dot(r, t2[0], mn(t2), mt(t2), t2[3]);
+    const double dm = row_dot(r, t3[0], mn(t3), mt(t3), t3[3]);
+    const double dd = row_dot(r, t4[0], mn(t4), mt(t4), t4[3]);
     // the TVB-modified minmod leaves a deviation within bound unchanged and
     // otherwise replaces it by minmod(deviation, dp, dm); the element is
     // troubled when a deviation changes. Both minmods are formed and the
@@ -172,108 +222,54 @@ __device__ __forceinline__ void limit_direction(const CharState& s, const double
     // to zero on division, which needs h > 1)
     sc[a] = minmod3(dd, dp, dm) / h;
   }
-  const int comp[4] = {0, in, it, 3};
+  double sn = 0.0, st = 0.0;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     double r[4];
-    right_row<AX>(s, a, r);
-    slope[comp[a]] = row_dot(r, sc[0], sc[1], sc[2], sc[3]);
+    right_row(s, un, ut, a, r);
+    const double o = row_dot(r, sc[0], sc[1], sc[2], sc[3]);
+    if (a == 0) sl[0] = o;
+    if (a == 1) sn = o;
+    if (a == 2) st = o;
+    if (a == 3) sl[3] = o;
   }
-}
-
-// ---------------------------------------------------- detect and limit --
-// Detection and limited slopes of element e: its mean qb, and slope[ax]
-// (d/dx, d/dy of the linear reconstruction) and troubled as the TVB
-// characteristic test decides. False when the mean density is not positive.
-template <int P>
-__device__ __forceinline__ bool limit_element(const Geometry& G, const WTab<P + 1>& W,
-                                              const LimitArgs& A, int e, double qb[4],
-                                              double slope[2][4], bool& troubled) {
-  constexpr int N1 = P + 1, NSP = N1 * N1;
-  const int I = e % G.nx, J = e / G.nx;
-  const int ne = G.nx * G.ny;
-  const size_t plane = (size_t)ne * NSP;
-
-  double fW[4], fE[4], fS[4], fN[4];
-  int Iw = I - 1, Ie = I + 1, Js = J - 1, Jn = J + 1;
-  if (G.periodic) {
-    Iw = (Iw + G.nx) % G.nx; Ie = Ie % G.nx;
-    Js = (Js + G.ny) % G.ny; Jn = Jn % G.ny;
-  } else {
-    Iw = max(Iw, 0); Ie = min(Ie, G.nx - 1);
-    Js = max(Js, 0); Jn = min(Jn, G.ny - 1);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double* q = A.q + k * plane + (size_t)e * NSP;
-    double w_ = 0.0, e_ = 0.0, s_ = 0.0, n_ = 0.0;
-#pragma unroll
-    for (int j = 0; j < N1; ++j) {
-      double rw = 0.0, re = 0.0, cs = 0.0, cn = 0.0;
-#pragma unroll
-      for (int i = 0; i < N1; ++i) {
-        rw = fma(W.em[i], q[j * N1 + i], rw);  // row j extrapolated west
-        re = fma(W.ep[i], q[j * N1 + i], re);
-        cs = fma(W.em[i], q[i * N1 + j], cs);  // column j extrapolated south
-        cn = fma(W.ep[i], q[i * N1 + j], cn);
-      }
-      w_ = fma(W.w[j], rw, w_);
-      e_ = fma(W.w[j], re, e_);
-      s_ = fma(W.w[j], cs, s_);
-      n_ = fma(W.w[j], cn, n_);
-    }
-    fW[k] = 0.5 * w_;
-    fE[k] = 0.5 * e_;
-    fS[k] = 0.5 * s_;
-    fN[k] = 0.5 * n_;
-    qb[k] = A.qbar[k * ne + e];
-  }
-  if (!(qb[0] > 0.0)) return false;
-
-  const CharState cs = char_state(qb, G.gamma);
-  troubled = false;
-  {
-    double nW[4], nE[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      nW[k] = A.qbar[k * ne + J * G.nx + Iw];
-      nE[k] = A.qbar[k * ne + J * G.nx + Ie];
-    }
-    limit_direction<0>(cs, qb, fW, fE, nW, nE, G.dx, A.tvb_m, troubled, slope[0]);
-  }
-  {
-    double nS[4], nN[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      nS[k] = A.qbar[k * ne + Js * G.nx + I];
-      nN[k] = A.qbar[k * ne + Jn * G.nx + I];
-    }
-    limit_direction<1>(cs, qb, fS, fN, nS, nN, G.dy, A.tvb_m, troubled, slope[1]);
-  }
+  sl[1] = y ? st : sn;  // rho u: normal on the x lane, tangential on the y lane
+  sl[2] = y ? sn : st;
   return true;
 }
 
+// Detect and limit, two lanes per element (limit_lane). The pair combines its
+// troubled flags and exchanges its slopes by lane shuffles; in a troubled
+// element each lane rewrites two of the four variables as the mean plus the
+// limited linear part.
 template <int P>
 __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, LimitArgs A) {
   constexpr int N1 = P + 1, NSP = N1 * N1;
   if (A.skip != nullptr && *A.skip != 0) return;  // the same for every block
   __shared__ int wave_count[4];
   const int ne = G.nx * G.ny;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tix = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = tix >> 1, d = tix & 1;  // both lanes of a pair are past ne together
   const size_t plane = (size_t)ne * NSP;
-  bool troubled = false;
-  double qb[4], slope[2][4];
-  if (e < ne) {
-    if (!limit_element<P>(G, W, A, e, qb, slope, troubled))
+  bool tr = false, ok = true;
+  double qb[4] = {0.0, 0.0, 0.0, 0.0}, sl[4] = {0.0, 0.0, 0.0, 0.0};
+  if (e < ne) ok = limit_lane<P>(G, W, A, e, d != 0, qb, sl, tr);
+  const bool troubled = tr | (__shfl_xor((int)tr, 1) != 0);
+  double so[4];  // the other lane's slope
+#pragma unroll
+  for (int k = 0; k < 4; ++k) so[k] = __shfl_xor(sl[k], 1);
+  if (e < ne && d == 0) {
+    if (!ok)
       atomicOr(A.err, 1);
     else if (A.flags != nullptr)
       A.flags[e] = troubled ? 1 : 0;
   }
 
-  // the block's troubled elements: one count per wave, summed by one thread;
-  // the running total has a slot per block, so no two blocks add to the
-  // same address (a thousand atomics on one address serialise at the L2)
-  const unsigned long long tw = __ballot(troubled);
+  // the block's troubled elements, counted on their x lanes: one count per
+  // wave, summed by one thread; the running total has a slot per block, so
+  // no two blocks add to the same address (a thousand atomics on one
+  // address serialise at the L2)
+  const unsigned long long tw = __ballot(troubled && d == 0 && e < ne);
   if ((threadIdx.x & 63) == 0) wave_count[threadIdx.x >> 6] = __popcll(tw);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -282,27 +278,34 @@ __global__ __launch_bounds__(256) void limit_kernel(Geometry G, WTab<P + 1> W, L
     if (A.count != nullptr && n != 0) atomicAdd(A.count, n);
     if (A.total != nullptr) A.total[blockIdx.x] += (unsigned long long)n;
   }
-  if (!troubled) return;
+  if (!troubled || e >= ne) return;
+  // variables 0 and 1 on the x lane, 2 and 3 on the y lane; each takes its
+  // x slope from the x lane and its y slope from the y lane
   const double hx = 0.5 * G.dx, hy = 0.5 * G.dy;
+  const double qa = d ? qb[2] : qb[0], qc = d ? qb[3] : qb[1];
+  const double sxa = d ? so[2] : sl[0], sya = d ? sl[2] : so[0];
+  const double sxc = d ? so[3] : sl[1], syc = d ? sl[3] : so[1];
+  double* pa = A.q + (size_t)(2 * d) * plane + (size_t)e * NSP;
+  double* pc = pa + plane;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    double* q = A.q + k * plane + (size_t)e * NSP;
+  for (int j = 0; j < N1; ++j)
 #pragma unroll
-    for (int j = 0; j < N1; ++j)
-#pragma unroll
-      for (int i = 0; i < N1; ++i)
-        q[j * N1 + i] = qb[k] + sym_dot2(slope[0][k], hx * W.xi[i], slope[1][k], hy * W.xi[j]);
-  }
+    for (int i = 0; i < N1; ++i) {
+      pa[j * N1 + i] = qa + sym_dot2(sxa, hx * W.xi[i], sya, hy * W.xi[j]);
+      pc[j * N1 + i] = qc + sym_dot2(sxc, hx * W.xi[i], syc, hy * W.xi[j]);
+    }
 }
 
-int limit_blocks(const Geometry& g) { return (g.nx * g.ny + 255) / 256; }
+// two lanes per element, 128 elements per block of 256
+int limit_blocks(const Geometry& g) { return (g.nx * g.ny + 127) / 128; }
 
 template <int P>
 static hipError_t launch_limit_t(const Geometry& g, const Tables1D& T, const LimitArgs& a,
                                  hipStream_t s) {
   const WTab<P + 1> w = make_wtab<P + 1>(T);
   const dim3 grid(limit_blocks(g)), block(256);
-  if (!a.means_ready) hipLaunchKernelGGL((means_kernel<P>), grid, block, 0, s, g, w, a);
+  if (!a.means_ready)  // one lane per element
+    hipLaunchKernelGGL((means_kernel<P>), dim3((g.nx * g.ny + 255) / 256), block, 0, s, g, w, a);
   hipLaunchKernelGGL((limit_kernel<P>), grid, block, 0, s, g, w, a);
   return hipGetLastError();
 }
