@@ -69,6 +69,34 @@ def test_limiter_matches_oracle(P, bc):
     assert np.max(np.abs(qg[:, both] - ql[:, both])) <= 1e-13 * max(1.0, np.max(np.abs(ql)))
 
 
+@pytest.mark.parametrize("P", [1, 2, 3, 4])
+@pytest.mark.parametrize("bc", ["transmissive", "periodic"])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 17), (23, 1), (37, 11)])
+def test_limiter_matches_oracle_degenerate_meshes(P, bc, nx, ny):
+    """The limiter on a single element, a single column, a single row (each
+    element its own neighbour across the periodic or transmissive boundary)
+    and 37x11 elements (the limiter runs two lanes per element, 128 elements
+    per workgroup: three full workgroups and a ragged fourth). The same bar
+    as above: flags agree outside the decision margin, values to 1e-13 where
+    the flags agree."""
+    g = cpr.Grid(P=P, nx=nx, ny=ny, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc=bc)
+    q = _blurred_riemann(g)
+    say("limiter degenerate mesh", P, bc, nx, ny)
+    M = 10.0
+    ql, flags = limiter.limit(q, g, M=M, return_flags=True)
+    s = make_solver(g, limiter=True, tvb_m=M)
+    qd = dev(q)
+    fd = torch().zeros((g.ny, g.nx), dtype=torch().int32, device="cuda")
+    n = s.limit(qd, flags=fd, count=True)
+    fg = host(fd).astype(bool)
+    safe = _margins(q, g, M) > 1e-9
+    assert np.array_equal(fg[safe], flags[safe])
+    assert n == int(fg.sum())
+    qg = host(qd)
+    agree = fg == flags
+    assert np.max(np.abs(qg[:, agree] - ql[:, agree])) <= 1e-13 * max(1.0, np.max(np.abs(ql)))
+
+
 def test_limited_rk3_riemann_steps_match_oracle():
     """Four-quadrant Riemann data on a 48x48 P=2 transmissive mesh, limiter
     after every stage: three steps at the oracle's CFL 0.1 dt. Stage inputs
